@@ -1,0 +1,326 @@
+"""Pins for the FP64 oracle: each test checks it against something other than
+itself (direct sums, an independent solver, spatial-domain circular shifts,
+closed forms, integrals, finite differences)."""
+import cmath
+import math
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import fdl_oracle as O
+
+
+# ---------------------------------------------------------------- DFT ------
+
+@pytest.mark.parametrize("H,W", [(8, 8), (6, 10), (12, 9), (9, 6)])
+def test_rfft2_matches_direct_sum(H, W):
+    rng = np.random.default_rng(1)
+    img = rng.standard_normal((H, W))
+    full = brute.naive_dft2(img)
+    np.testing.assert_allclose(O.rfft2(img), full[:, : W // 2 + 1], rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("H,W", [(8, 8), (6, 10), (10, 4)])
+def test_irfft2_drops_imag_of_self_conjugate_bins(H, W):
+    rng = np.random.default_rng(2)
+    half = rng.standard_normal((H, W // 2 + 1)) + 1j * rng.standard_normal((H, W // 2 + 1))
+    ref = brute.naive_idft2_real(brute.hermitian_extend(half, W))
+    np.testing.assert_allclose(O.irfft2(half, H, W), ref, rtol=0, atol=1e-12)
+    img = rng.standard_normal((H, W))
+    np.testing.assert_allclose(O.irfft2(O.rfft2(img), H, W), img, atol=1e-12)
+
+
+def test_frequency_grid_conventions():
+    wx, wy = O.freq_grid(8, 8)
+    assert wx[0, 4] == 0.5            # Nyquist column is +1/2
+    assert wy[4, 0] == -0.5           # Nyquist row is -1/2
+    assert wy[1, 0] == 0.125 and wy[7, 0] == -0.125
+
+
+# ------------------------------------------------------- A and M ----------
+
+def _explicit_A(u, d, wx, wy):
+    m, n = len(u), len(d)
+    A = np.zeros((m, n), dtype=np.complex128)
+    for j in range(m):
+        for k in range(n):
+            A[j, k] = cmath.exp(2j * math.pi * d[k] * (u[j][0] * wx + u[j][1] * wy))
+    return A
+
+
+def test_gram_dirichlet_closed_form_integer_grid():
+    """Integer grid {-R..R}^2: (A^H A)_{k1 k2} = D(th_x) D(th_y),
+    th = 2 pi (d_k2 - d_k1) w, D(t) = sin((2R+1) t / 2) / sin(t / 2)."""
+    R = 2
+    g = np.arange(-R, R + 1)
+    vv, uu = np.meshgrid(g, g, indexing="ij")
+    u = np.stack([uu.ravel(), vv.ravel()], 1).astype(float)
+    d = np.array([-1.3, -0.2, 0.7, 1.9])
+    wx = np.array([0.0, 0.11, 0.31, 0.5, 0.05])
+    wy = np.array([0.0, -0.23, 0.17, -0.5, 0.41])
+    A = O.a_matrix(u, d, wx, wy)
+    G = np.conj(np.swapaxes(A, 1, 2)) @ A
+
+    def dirichlet(t):
+        if abs(math.sin(t / 2)) < 1e-12:
+            return 2 * R + 1.0
+        return math.sin((2 * R + 1) * t / 2) / math.sin(t / 2)
+
+    for f in range(len(wx)):
+        for a in range(len(d)):
+            for b in range(len(d)):
+                dd = d[b] - d[a]
+                ref = dirichlet(2 * math.pi * dd * wx[f]) * dirichlet(2 * math.pi * dd * wy[f])
+                assert abs(G[f, a, b] - ref) < 1e-10
+        assert np.allclose(np.diag(G[f]).real, len(u), atol=1e-12)
+
+
+def test_a_matrix_against_explicit_loops():
+    rng = np.random.default_rng(3)
+    u = rng.uniform(-3, 3, (7, 2))
+    d = rng.uniform(-2, 2, 5)
+    wx = rng.uniform(0, 0.5, 4)
+    wy = rng.uniform(-0.5, 0.5, 4)
+    A = O.a_matrix(u, d, wx, wy)
+    for f in range(4):
+        np.testing.assert_allclose(A[f], _explicit_A(u, d, wx[f], wy[f]), atol=1e-13)
+
+
+# --------------------------------------------------------- construct ------
+
+def _tiny_problem(seed, m=6, n=4, C=2, H=8, W=8):
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-2, 2, (m, 2))
+    d = np.sort(rng.uniform(-2, 2, n))
+    imgs = rng.standard_normal((m, C, H, W))
+    return u, d, O.rfft2(imgs)
+
+
+@pytest.mark.parametrize("reg", [O.REG_VIEW2, O.REG_LAYER2, O.REG_L2])
+def test_construct_matches_stacked_least_squares(reg):
+    H, W = 8, 8
+    u, d, spec = _tiny_problem(4, H=H, W=W)
+    lam, eps = 0.3, 1e-2
+    x = O.construct(spec, u, d, H, W, lam, eps, reg)
+    wx, wy = O.freq_grid(H, W)
+    m, C = spec.shape[:2]
+    n = len(d)
+    for ky in range(H):
+        for kx in range(W // 2 + 1):
+            A = _explicit_A(u, d, wx[ky, kx], wy[ky, kx])
+            if reg == O.REG_VIEW2:
+                w2 = wx[ky, kx] ** 2 + wy[ky, kx] ** 2
+                Gam = np.diag(w2 * d ** 2)
+            elif reg == O.REG_LAYER2:
+                Gam = -2 * np.eye(n) + np.eye(n, k=1) + np.eye(n, k=-1)
+            else:
+                Gam = np.eye(n)
+            ref = brute.stacked_lstsq(A, spec[:, :, ky, kx], Gam, lam, eps)
+            np.testing.assert_allclose(x[:, :, ky, kx], ref, rtol=1e-9, atol=1e-9)
+
+
+def test_construct_dc_closed_form():
+    """At w = 0 every A_jk = 1 and the view regulariser vanishes, so
+    x_k(0) = sum_j b_j / (m n + eps) for every layer."""
+    H, W = 8, 8
+    u, d, spec = _tiny_problem(5, m=9, n=5, H=H, W=W)
+    eps = 1e-3
+    x = O.construct(spec, u, d, H, W, 0.7, eps, O.REG_VIEW2)
+    m, n = 9, 5
+    ref = spec[:, :, 0, 0].sum(axis=0) / (m * n + eps)
+    for k in range(n):
+        np.testing.assert_allclose(x[k, :, 0, 0], ref, rtol=1e-9)  # cond(M) ~ mn/eps
+
+
+def _roll_views(layers, u_int, d_int):
+    """Views from spatial layers by circular shifts: view_j(y, x) =
+    sum_k layer_k(y + v_j d_k, x + u_j d_k) (Eq. Prior1 with integer shifts),
+    no Fourier arithmetic."""
+    n, C, H, W = layers.shape
+    out = np.zeros((len(u_int), C, H, W))
+    for j, (uj, vj) in enumerate(u_int):
+        for k in range(n):
+            out[j] += np.roll(layers[k], (-vj * d_int[k], -uj * d_int[k]), axis=(-2, -1))
+    return out
+
+
+def test_construct_exact_recovery_of_band_limited_layers():
+    """Noise-free views of layers whose spectra live only where A is well
+    conditioned are inverted exactly when lambda, eps -> 0."""
+    H, W = 16, 16
+    u_int = [(a, b) for b in (-1, 0, 1) for a in (-1, 0, 1)]
+    d_int = [-1, 0, 2]
+    rng = np.random.default_rng(6)
+    layers = rng.standard_normal((3, 1, H, W))
+    spec = O.rfft2(layers)
+    wx, wy = O.flat_freqs(H, W)
+    A = O.a_matrix(np.array(u_int, float), np.array(d_int, float), wx, wy)
+    cond = np.linalg.cond(A).reshape(H, W // 2 + 1)
+    spec[:, :, cond >= 1e3] = 0.0
+    layers = O.irfft2(spec, H, W)
+    spec = O.rfft2(layers)
+    assert (cond < 1e3).mean() > 0.5
+    views = _roll_views(layers, u_int, d_int)
+    x = O.construct(O.rfft2(views), np.array(u_int, float), np.array(d_int, float), H, W,
+                    1e-12, 1e-12, O.REG_VIEW2)
+    assert O.rel_l2(x, spec) < 1e-7
+
+
+def test_construct_reproduces_input_views():
+    """All-band layers are not identifiable, but with lambda, eps -> 0 the
+    layers rendered back at the input positions reproduce the views."""
+    H, W = 16, 16
+    u_int = [(a, b) for b in (-1, 0, 1) for a in (-1, 0, 1)]
+    d_int = [-2, -1, 0, 1, 2]
+    rng = np.random.default_rng(7)
+    layers = rng.standard_normal((5, 2, H, W))
+    views = _roll_views(layers, u_int, d_int)
+    u = np.array(u_int, float)
+    d = np.array(d_int, float)
+    x = O.construct(O.rfft2(views), u, d, H, W, 1e-12, 1e-12, O.REG_VIEW2)
+    rv = np.zeros((9, 5))
+    rv[:, :2] = u
+    back = O.render_images(x, d, rv, H, W)
+    assert O.rel_l2(back, views) < 1e-6
+
+
+def test_construct_sampled_bins_match_full():
+    H, W = 8, 12
+    u, d, spec = _tiny_problem(8, H=H, W=W)
+    full = O.construct(spec, u, d, H, W, 0.1, 1e-3)
+    idx = np.array([0, 5, 17, 30, 55])
+    part = O.construct(spec, u, d, H, W, 0.1, 1e-3, freq_index=idx)
+    np.testing.assert_allclose(part, full.reshape(len(d), spec.shape[1], -1)[:, :, idx], atol=1e-13)
+
+
+# ------------------------------------------------------------ render ------
+
+def test_render_integer_shift_is_circular_roll():
+    H, W = 12, 16
+    rng = np.random.default_rng(9)
+    layer = rng.standard_normal((1, 1, H, W))
+    spec = O.rfft2(layer)
+    for (u0, v0, dk) in [(1, 0, 2), (-2, 1, 1), (1, -1, -3)]:
+        img = O.render_images(spec, np.array([float(dk)]), np.array([[u0, v0, 0, 0, 0]], float), H, W)
+        ref = np.roll(layer[0], (-v0 * dk, -u0 * dk), axis=(-2, -1))
+        np.testing.assert_allclose(img[0], ref, atol=1e-12)
+
+
+def test_render_zero_radius_is_pinhole_and_in_focus_layer_is_sharp():
+    H, W = 8, 8
+    rng = np.random.default_rng(10)
+    x = O.rfft2(rng.standard_normal((3, 1, H, W)))
+    d = np.array([-1.0, 0.5, 2.0])
+    pin = O.render(x, d, np.array([[0.3, -0.7, 0.0, 0.0, 0]]), H, W)
+    for shape in (1, 2):
+        r0 = O.render(x, d, np.array([[0.3, -0.7, 1.1, 0.0, shape]]), H, W)
+        np.testing.assert_allclose(r0, pin, atol=1e-12)
+        # only layer 1 present and focused on it: the aperture has no effect
+        x1 = np.zeros_like(x)
+        x1[1] = x[1]
+        a = O.render(x1, d, np.array([[0.3, -0.7, 0.5, 1.7, shape]]), H, W)
+        b = O.render(x1, d, np.array([[0.3, -0.7, 0.0, 0.0, 0]]), H, W)
+        np.testing.assert_allclose(a, b, atol=1e-12)
+
+
+@pytest.mark.parametrize("shape,rho", [(1, 0.8), (1, 1.7), (2, 0.6), (2, 1.3)])
+def test_aperture_spectrum_against_quadrature(shape, rho):
+    for xi in [(0.0, 0.0), (0.13, -0.21), (0.41, 0.07), (-0.3, 0.33)]:
+        q = brute.aperture_quadrature(shape, rho, xi[0], xi[1], N=1201)
+        a = float(O.psi_hat(shape, rho, np.array([xi[0]]), np.array([xi[1]]))[0])
+        assert abs(a - q) < 2e-3, (shape, rho, xi, a, q)
+
+
+def test_render_matches_refocus_integral():
+    """Eq. BsFourier against its defining integral Eq. BsIntermediate."""
+    rng = np.random.default_rng(11)
+    n = 3
+    d = np.array([-1.2, 0.1, 0.9])
+    Lb = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+    wx, wy = 0.19, -0.27
+    for (u0, v0, s, shape, rho) in [(0.4, -0.3, 0.5, 1, 0.9), (-1.0, 0.6, -0.7, 2, 0.7)]:
+        # evaluate closed form at a single bin through psi_hat
+        acc = 0j
+        for k in range(n):
+            acc += (cmath.exp(2j * math.pi * d[k] * (u0 * wx + v0 * wy))
+                    * O.psi_hat(shape, rho, np.array([(s - d[k]) * wx]), np.array([(s - d[k]) * wy]))[0]
+                    * Lb[k])
+        q = brute.refocus_quadrature(Lb, d, u0, v0, s, shape, rho, wx, wy, N=801)
+        assert abs(acc - q) < 3e-3 * (1 + abs(q)), (acc, q)
+
+
+# ------------------------------------------------------- calibration ------
+
+def _calib_case(seed=12, m=5, n=3, H=8, W=8, C=1):
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-1.5, 1.5, (m, 2))
+    d = np.sort(rng.uniform(-1.5, 1.5, n))
+    spec = O.rfft2(rng.standard_normal((m, C, H, W)))
+    F = H * (W // 2 + 1)
+    return u, d, spec, np.arange(1, F)
+
+
+@pytest.mark.parametrize("reg", [O.REG_LAYER2, O.REG_VIEW2])
+def test_fit_gradient_matches_finite_differences(reg):
+    """Eq. gradP / gradD (envelope theorem) against central differences.
+    With the view regulariser the regulariser depends on d, so only the
+    u-gradient is exact there (the paper's reason for the layer regulariser)."""
+    H, W = 8, 8
+    u, d, spec, S = _calib_case()
+    lam, eps = 1e-2, 1e-3
+    _, gu, gd = O.calib_fit_loss_grad(spec, u, d, H, W, lam, eps, reg, S)
+    fu = brute.central_fd(lambda uu: O.calib_fit_loss_grad(spec, uu, d, H, W, lam, eps, reg, S)[0], u)
+    np.testing.assert_allclose(gu, fu, rtol=1e-6, atol=1e-9 * np.abs(fu).max())
+    if reg == O.REG_LAYER2:
+        fd = brute.central_fd(lambda dd: O.calib_fit_loss_grad(spec, u, dd, H, W, lam, eps, reg, S)[0], d)
+        np.testing.assert_allclose(gd, fd, rtol=1e-6, atol=1e-9 * np.abs(fd).max())
+
+
+def test_loo_loss_matches_press_identity():
+    H, W = 8, 8
+    u, d, spec, S = _calib_case(seed=13, C=2)
+    lam, eps = 1e-2, 1e-3
+    loss = O.calib_loo_loss(spec, u, d, H, W, lam, eps, O.REG_LAYER2, S)
+    wx, wy = O.flat_freqs(H, W)
+    RtR = O.second_difference(len(d))
+    RtR = RtR.T @ RtR
+    m, C = spec.shape[:2]
+    tot = 0.0
+    for f in S:
+        A = _explicit_A(u, d, wx[f], wy[f])
+        b = spec.reshape(m, C, -1)[:, :, f] / math.sqrt(H * W)
+        tot += np.sum(np.abs(brute.press_residuals(A, b, RtR, lam, eps)) ** 2)
+    assert abs(loss - tot / len(S)) < 1e-10 * abs(loss)
+
+
+def test_loo_gradient_matches_finite_differences():
+    H, W = 8, 8
+    u, d, spec, S = _calib_case(seed=14)
+    S = S[::3]
+    lam, eps = 1e-2, 1e-3
+    _, gu, gd = O.calib_loo_loss_grad(spec, u, d, H, W, lam, eps, O.REG_LAYER2, S)
+    f = lambda uu, dd: O.calib_loo_loss(spec, uu, dd, H, W, lam, eps, O.REG_LAYER2, S)
+    fu = brute.central_fd(lambda uu: f(uu, d), u)
+    fd = brute.central_fd(lambda dd: f(u, dd), d)
+    np.testing.assert_allclose(gu, fu, rtol=1e-6, atol=1e-9 * np.abs(fu).max())
+    np.testing.assert_allclose(gd, fd, rtol=1e-6, atol=1e-9 * np.abs(fd).max())
+
+
+@pytest.mark.parametrize("mode", [O.LOSS_FIT, O.LOSS_LOO])
+def test_gradient_gauge_identity(mode):
+    """Any loss of P = u d^T satisfies sum_j <u_j, grad u_j> = sum_k d_k grad d_k
+    (scaling u by a and d by 1/a leaves P unchanged)."""
+    H, W = 8, 8
+    u, d, spec, S = _calib_case(seed=15)
+    _, gu, gd = O.calib_loss_grad(spec, u, d, H, W, 1e-2, 1e-3, O.REG_LAYER2, mode, S)
+    lhs = np.sum(u * gu)
+    rhs = np.sum(d * gd)
+    assert abs(lhs - rhs) < 1e-9 * (abs(lhs) + abs(rhs))
+
+
+def test_gd_step_hand_values():
+    u2, d2 = O.gd_step(np.array([[1.0, 0.0]]), np.array([2.0]), np.array([[2.0, 0.0]]), np.array([0.5]),
+                       alpha=0.2, eps_g=0.0)
+    np.testing.assert_allclose(u2, [[0.9, 0.0]])
+    np.testing.assert_allclose(d2, [1.6])
