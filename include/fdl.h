@@ -1,0 +1,223 @@
+/*
+ * fdl.h -- C ABI of the MI355X Fourier Disparity Layer library (libfdl.so).
+ *
+ * The library implements the per-frequency hot path of the Fourier Disparity
+ * Layer (FDL) representation (Le Pendu, Guillemot, Smolic, "A Fourier
+ * Disparity Layer representation for Light Fields"):
+ *   - the 2D real DFT of the input views and its inverse (Sec. V-A, Sec. VII),
+ *   - layer construction: at every spatial frequency w a regularised least
+ *     squares solve x = (A^H A + lambda Gamma^H Gamma + eps I)^-1 A^H b
+ *     (Eq. LayerConstructionClosedForm) with A_jk = exp(+2 pi i d_k <u_j, w>)
+ *     (Eq. AMatGeneral for sub-aperture inputs),
+ *   - rendering: B(w) = sum_k exp(+2 pi i d_k <u0, w>) psi_hat((s - d_k) w) L_k(w)
+ *     (Eq. BsFourier),
+ *   - the calibration objective and its gradient with respect to the view
+ *     positions u_j and disparities d_k (Eqs. CalibrationProb, gradD, gradP),
+ *     and a leave-one-out variant with a hand-written adjoint,
+ *   - the normalised gradient step on (u, d) (Sec. V-B),
+ *   - a batched construction of many uneven light fields in one persistent
+ *     launch (a plan object, so the launch can be captured in a HIP graph).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named *_dev are DEVICE pointers (hipMalloc / torch CUDA tensors),
+ *    contiguous, in the layouts stated below.  The caller owns every buffer;
+ *    the library keeps no pointer after a call returns (plans excepted, see
+ *    there).
+ *  - Spectra are complex64 interleaved (re, im), half spectrum of a real
+ *    image: [..][H][W/2+1], bin f = ky*(W/2+1) + kx, unnormalised forward DFT
+ *    sum_x img(x) exp(-2 pi i <x, w>).  Frequencies are in cycles/pixel:
+ *    w_x = kx/W (kx = 0..W/2), w_y = ky/H for ky < H/2 else (ky-H)/H.
+ *  - A view position is (u, v) = (horizontal, vertical) in view-grid units;
+ *    disparities are pixels per unit of position.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).  All
+ *    compute entry points enqueue asynchronously on it and never synchronise.
+ *  - Return value: FDL_OK or a negative fdl_status.  Argument and shape errors
+ *    are detected on the host before anything is enqueued; HIP launch errors
+ *    are returned as FDL_EHIP.  Numerical events detected on the device (a
+ *    non-positive Cholesky pivot) are counted into an optional device int32.
+ */
+#ifndef FDL_H
+#define FDL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct { float re, im; } fdl_c64;          /* == torch.complex64 element */
+typedef struct { float x, y; } fdl_f2;             /* view position (u, v) */
+
+/* One render request: position (u, v), focus disparity s, aperture radius rho
+ * (view units; disk radius or square half-side, 0 = pinhole) and shape. */
+typedef struct { float u, v, focus, radius; int32_t shape; } fdl_view;
+
+enum fdl_status {
+  FDL_OK = 0,
+  FDL_EINVAL = -1,        /* null pointer, non-finite or out-of-range scalar */
+  FDL_ESHAPE = -2,        /* unsupported size (see each entry point) */
+  FDL_ENOMEM = -3,        /* workspace too small / device allocation failed */
+  FDL_EHIP = -4,          /* HIP runtime or launch error */
+  FDL_ENUMERIC = -5,      /* reserved for numerical failures reported on the host */
+  FDL_EUNSUPPORTED = -6   /* valid request this build does not implement */
+};
+
+enum fdl_reg {
+  FDL_REG_VIEW2 = 0,      /* lambda diag(|w|^4 d_k^4): Eq. 2ndOrderView (2D, r -> inf) */
+  FDL_REG_LAYER2 = 1,     /* lambda Gamma^T Gamma, Gamma = tridiag(1,-2,1): Eq. 2ndOrderLayer */
+  FDL_REG_L2 = 2          /* lambda I (classical l2, Sec. V-C) */
+};
+
+enum fdl_loss {
+  FDL_LOSS_FIT = 0,       /* Eq. CalibrationProb, gradient by Eqs. gradP/gradD */
+  FDL_LOSS_LOO = 1        /* leave-one-out view prediction error, exact adjoint */
+};
+
+enum fdl_aperture {
+  FDL_AP_PINHOLE = 0,     /* psi = delta, psi_hat = 1 */
+  FDL_AP_DISK = 1,        /* unit-integral disk of radius rho: 2 J1(z)/z, z = 2 pi rho |xi| */
+  FDL_AP_SQUARE = 2       /* unit-integral square of half-side rho: sinc(2 rho xi_x) sinc(2 rho xi_y) */
+};
+
+/* Limits of this build. */
+#define FDL_MAX_LAYERS 32
+#define FDL_MAX_CHANNELS 4
+
+/* Human-readable text for a status code (static storage). */
+const char* fdl_status_string(int code);
+
+/* Library version: major*10000 + minor*100 + patch. */
+int fdl_version(void);
+
+/* ---------------------------------------------------------------------------
+ * Real 2D DFT (Sec. V-A "compute the discrete Fourier transform of each
+ * image"; Sec. VII: only the Hermitian half is computed).
+ *   img_dev  [batch][H][W] float32  ->  spec_dev [batch][H][W/2+1] complex64.
+ * Unnormalised (numpy "backward" convention).  H and W must each be a
+ * product of powers of 2 and 3, 4 <= W <= 4096, 2 <= H <= 4096, W even.
+ * Returns FDL_ESHAPE otherwise.  In-place is not supported.
+ * ------------------------------------------------------------------------- */
+int fdl_rfft2(const float* img_dev, fdl_c64* spec_dev, int batch, int H, int W, void* stream);
+
+/* Inverse of fdl_rfft2 with 1/(H W) normalisation:
+ *   spec_dev [batch][H][W/2+1] complex64 -> img_dev [batch][H][W] float32.
+ * The half spectrum is extended by Hermitian symmetry; the imaginary parts of
+ * self-conjugate bins (DC/Nyquist rows of columns kx = 0 and kx = W/2) do not
+ * contribute (numpy irfft2 semantics).  Same size rules as fdl_rfft2. */
+int fdl_irfft2(const fdl_c64* spec_dev, float* img_dev, int batch, int H, int W, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Layer construction (Sec. V-A, Eq. LayerConstructProb and its closed form
+ * Eq. LayerConstructionClosedForm), sub-aperture inputs (psi_j = delta).
+ *
+ * For every half-spectrum bin w, independently:
+ *   A_jk = exp(+2 pi i d_k <u_j, w>)                       (m x n)
+ *   M    = A^H A + lambda R(w) + eps I                     (n x n, Hermitian PD)
+ *   x_c  = M^-1 A^H b_c  for each channel c                (M shared by channels)
+ * with R(w) = diag(|w|^4 d_k^4) (FDL_REG_VIEW2), tridiag(1,-2,1)^T tridiag(1,-2,1)
+ * (FDL_REG_LAYER2) or I (FDL_REG_L2); eps is the small diagonal term that makes
+ * the DC bin solvable (remark after Eq. 2ndOrderView), added outside lambda.
+ *
+ *   view_spec_dev  [m][C][H][W/2+1] complex64  (b_j = spectrum of view j)
+ *   u_dev          [m] fdl_f2                  view positions
+ *   d_dev          [n] float32                 layer disparities (any values)
+ *   layer_spec_dev [n][C][H][W/2+1] complex64  output layer spectra
+ *   status_dev     int32 device counter or NULL: incremented once per bin whose
+ *                  Cholesky factorisation met a non-positive pivot (the pivot
+ *                  is then replaced by a tiny positive value and the result is
+ *                  not meaningful for that bin).
+ * Requires 1 <= m <= 4096, 1 <= n <= FDL_MAX_LAYERS, 1 <= C <= FDL_MAX_CHANNELS,
+ * H >= 1, W >= 2 even, lambda >= 0, eps >= 0 (eps > 0 needed for a solvable DC
+ * bin with the view regulariser).  The solve is carried out in FP64 from the
+ * complex64 inputs; outputs are rounded to complex64.
+ * ------------------------------------------------------------------------- */
+int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_dev,
+                  int m, int n, int C, int H, int W, float lambda, float eps, int reg,
+                  fdl_c64* layer_spec_dev, int32_t* status_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Rendering (Sec. IV-B Eq. BsFourier; Sec. VI): for each request v and bin w
+ *   B_v(w) = sum_k exp(+2 pi i d_k <(u_v, v_v), w>) psi_hat_v((s_v - d_k) w) L_k(w)
+ * with unit-integral apertures (psi_hat(0) = 1; radius 0 is a sub-aperture
+ * view for every shape).
+ *
+ *   layer_spec_dev [n][C][H][W/2+1] complex64
+ *   d_dev          [n] float32
+ *   views_dev      [V] fdl_view
+ *   out_spec_dev   [V][C][H][W/2+1] complex64
+ * Requires 1 <= n <= FDL_MAX_LAYERS, 1 <= C <= FDL_MAX_CHANNELS, V >= 1,
+ * W >= 2 even.  Shapes outside {PINHOLE, DISK, SQUARE} render as pinhole.
+ * ------------------------------------------------------------------------- */
+int fdl_render(const fdl_c64* layer_spec_dev, const float* d_dev, int n, int C, int H, int W,
+               const fdl_view* views_dev, int V, fdl_c64* out_spec_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Calibration loss and gradient (Sec. V-B).  Over the Q bins freq_idx_dev
+ * (flat half-spectrum indices, or all F = H(W/2+1) bins when freq_idx_dev is
+ * NULL), with orthonormal spectra b = view_spec / sqrt(H W):
+ *
+ * FDL_LOSS_FIT (Eq. CalibrationProb):
+ *   E = (1/Q) sum_q [ ||A x_q - b_q||^2 + lambda ||Gamma x_q||^2 + eps ||x_q||^2 ],
+ *   x_q the minimiser; gradient by Eqs. gradP / gradD generalised to 2D:
+ *   G_jk = 4 pi Im(conj(x_k) conj(A_jk) r_j), r = A x - b,
+ *   grad u_j = (1/Q) sum_q sum_k d_k G_jk w_q, grad d_k = (1/Q) sum_q sum_j G_jk <u_j, w_q>.
+ *   Exact when the regulariser does not depend on d (FDL_REG_LAYER2, FDL_REG_L2).
+ * FDL_LOSS_LOO (leave-one-out view prediction):
+ *   E = (1/Q) sum_q sum_j |r_j / (1 - h_jj)|^2, r = b - A x, h_jj = a_j M^-1 a_j^H,
+ *   which equals the error of predicting view j from the layers fitted without
+ *   it; the gradient back-propagates through M^-1 (hand-written adjoint).
+ *
+ *   loss_dev   [1] double, grad_u_dev [m][2] double, grad_d_dev [n] double.
+ *   ws_dev / ws_bytes: device workspace of at least fdl_calib_workspace(m, n, Q)
+ *   bytes (per-block partial sums; reduced deterministically on the device).
+ * Requires 1 <= m <= 256, 1 <= n <= FDL_MAX_LAYERS, 1 <= C <= FDL_MAX_CHANNELS,
+ * Q >= 1 when freq_idx_dev != NULL, every index in [0, F).
+ * ------------------------------------------------------------------------- */
+size_t fdl_calib_workspace(int m, int n, int Q);
+int fdl_calib_grad(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_dev,
+                   int m, int n, int C, int H, int W, float lambda, float eps, int reg, int mode,
+                   const int32_t* freq_idx_dev, int Q,
+                   double* loss_dev, double* grad_u_dev, double* grad_d_dev,
+                   void* ws_dev, size_t ws_bytes, void* stream);
+
+/* The normalised gradient step of Sec. V-B on the device:
+ *   u <- u - alpha grad_u / (eps_g + ||grad_u||^2),  d <- d - alpha grad_d / (eps_g + ||grad_d||^2)
+ * (squared norms as printed; alpha = 0.2 in the paper).  Computed in FP64,
+ * stored back to the float32 parameters.  u_dev [m] fdl_f2, d_dev [n] float32. */
+int fdl_gd_step(fdl_f2* u_dev, float* d_dev, const double* grad_u_dev, const double* grad_d_dev,
+                int m, int n, double alpha, double eps_g, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Batched construction of uneven light fields (same mathematics as
+ * fdl_construct for each light field) in ONE persistent kernel launch.
+ *
+ * fdl_batch_plan_create reads a HOST array of B descriptors, validates them,
+ * chooses the launch shape (from the autotune table when one is loaded), and
+ * uploads the descriptors and a work table to device memory it allocates.
+ * The plan keeps the device pointers of the descriptors until it is destroyed:
+ * the buffers they point at must stay valid while the plan is executed.
+ * fdl_batch_plan_execute only enqueues the kernel (graph-capturable).
+ * ------------------------------------------------------------------------- */
+typedef struct fdl_lf_desc {
+  const fdl_c64* view_spec;   /* device [m][C][H][W/2+1] */
+  const fdl_f2* u;            /* device [m] */
+  const float* d;             /* device [n] */
+  fdl_c64* layer_spec;        /* device [n][C][H][W/2+1] output */
+  int32_t* status;            /* device counter or NULL */
+  int32_t m, n, C, H, W, reg;
+  float lambda, eps;
+} fdl_lf_desc;
+
+typedef struct fdl_batch_plan fdl_batch_plan;
+
+int fdl_batch_plan_create(const fdl_lf_desc* descs_host, int B, int tile_bins, fdl_batch_plan** plan_out);
+int fdl_batch_plan_execute(const fdl_batch_plan* plan, void* stream);
+int fdl_batch_plan_info(const fdl_batch_plan* plan, int64_t* total_bins, int32_t* grid, int32_t* tile_bins);
+int fdl_batch_plan_destroy(fdl_batch_plan* plan);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDL_H */

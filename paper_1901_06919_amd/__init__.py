@@ -1,0 +1,224 @@
+"""MI355X Fourier Disparity Layers: Python binding of libfdl.so.
+
+Thin ctypes marshalling over the C ABI declared in ``include/fdl.h``: every
+function takes torch CUDA tensors (device memory and the current stream are
+the only things torch provides), checks dtypes/shapes/devices, and calls the
+library entry point of the same name.  All arithmetic happens in the HIP
+kernels; there is no CPU fallback -- if the library is missing the call
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch  # must be imported before libfdl.so so both share one HIP runtime
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfdl.so")
+
+REG_VIEW2 = 0
+REG_LAYER2 = 1
+REG_L2 = 2
+LOSS_FIT = 0
+LOSS_LOO = 1
+AP_PINHOLE = 0
+AP_DISK = 1
+AP_SQUARE = 2
+MAX_LAYERS = 32
+MAX_CHANNELS = 4
+
+_lib = None
+
+
+class FDLError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        self.code = code
+        msg = lib().fdl_status_string(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{fn} failed: {msg} ({code})")
+
+
+def lib():
+    """Load libfdl.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} not found: run `python -m paper_1901_06919_amd.build` first")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, f32, f64, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_float, ctypes.c_double, ctypes.c_size_t
+    L.fdl_status_string.restype = ctypes.c_char_p
+    L.fdl_status_string.argtypes = [i32]
+    L.fdl_version.restype = i32
+    L.fdl_version.argtypes = []
+    L.fdl_construct.restype = i32
+    L.fdl_construct.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, vp, vp, vp]
+    L.fdl_render.restype = i32
+    L.fdl_render.argtypes = [vp, vp, i32, i32, i32, i32, vp, i32, vp, vp]
+    for name in ("fdl_rfft2", "fdl_irfft2"):
+        if hasattr(L, name):
+            fn = getattr(L, name)
+            fn.restype = i32
+            fn.argtypes = [vp, vp, i32, i32, i32, vp]
+    if hasattr(L, "fdl_calib_grad"):
+        L.fdl_calib_workspace.restype = sz
+        L.fdl_calib_workspace.argtypes = [i32, i32, i32]
+        L.fdl_calib_grad.restype = i32
+        L.fdl_calib_grad.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, i32,
+                                     vp, i32, vp, vp, vp, vp, sz, vp]
+        L.fdl_gd_step.restype = i32
+        L.fdl_gd_step.argtypes = [vp, vp, vp, vp, i32, i32, f64, f64, vp]
+    if hasattr(L, "fdl_batch_plan_create"):
+        L.fdl_batch_plan_create.restype = i32
+        L.fdl_batch_plan_create.argtypes = [vp, i32, i32, ctypes.POINTER(vp)]
+        L.fdl_batch_plan_execute.restype = i32
+        L.fdl_batch_plan_execute.argtypes = [vp, vp]
+        L.fdl_batch_plan_info.restype = i32
+        L.fdl_batch_plan_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(i32),
+                                          ctypes.POINTER(i32)]
+        L.fdl_batch_plan_destroy.restype = i32
+        L.fdl_batch_plan_destroy.argtypes = [vp]
+    _lib = L
+    return L
+
+
+def _stream(t: torch.Tensor) -> int:
+    return torch.cuda.current_stream(t.device).cuda_stream
+
+
+def _check(t: torch.Tensor, dtype, shape, name: str):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _call(fn: str, *args):
+    code = getattr(lib(), fn)(*args)
+    if code != 0:
+        raise FDLError(fn, code)
+
+
+def view_records(views: torch.Tensor) -> torch.Tensor:
+    """[V, 5] float rows (u, v, focus, radius, shape) -> device fdl_view records
+    (the same 20 bytes per row, shape stored as int32)."""
+    v = views.to(torch.float32).contiguous().clone()
+    v[:, 4] = views[:, 4].round().to(torch.int32).view(torch.float32)
+    return v
+
+
+def rfft2(img: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """[..., H, W] float32 -> [..., H, W//2+1] complex64 (fdl_rfft2)."""
+    H, W = img.shape[-2:]
+    batch = img.numel() // (H * W)
+    if out is None:
+        out = torch.empty(img.shape[:-1] + (W // 2 + 1,), dtype=torch.complex64, device=img.device)
+    _check(img, torch.float32, None, "img")
+    _check(out, torch.complex64, img.shape[:-1] + (W // 2 + 1,), "out")
+    _call("fdl_rfft2", img.data_ptr(), out.data_ptr(), batch, H, W, _stream(img))
+    return out
+
+
+def irfft2(spec: torch.Tensor, H: int, W: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """[..., H, W//2+1] complex64 -> [..., H, W] float32 (fdl_irfft2)."""
+    batch = spec.numel() // (H * (W // 2 + 1))
+    if out is None:
+        out = torch.empty(spec.shape[:-1] + (W,), dtype=torch.float32, device=spec.device)
+    _check(spec, torch.complex64, spec.shape[:-2] + (H, W // 2 + 1), "spec")
+    _check(out, torch.float32, spec.shape[:-1] + (W,), "out")
+    _call("fdl_irfft2", spec.data_ptr(), out.data_ptr(), batch, H, W, _stream(spec))
+    return out
+
+
+def construct(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int, W: int,
+              lam: float, eps: float, reg: int = REG_VIEW2, out: Optional[torch.Tensor] = None,
+              status: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Layer spectra [n, C, H, W//2+1] from view spectra [m, C, H, W//2+1] (fdl_construct)."""
+    m, C = view_spec.shape[:2]
+    n = d.shape[0]
+    _check(view_spec, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
+    _check(u, torch.float32, (m, 2), "u")
+    _check(d, torch.float32, (n,), "d")
+    if out is None:
+        out = torch.empty((n, C, H, W // 2 + 1), dtype=torch.complex64, device=view_spec.device)
+    _check(out, torch.complex64, (n, C, H, W // 2 + 1), "out")
+    sp = 0
+    if status is not None:
+        _check(status, torch.int32, (1,), "status")
+        sp = status.data_ptr()
+    _call("fdl_construct", view_spec.data_ptr(), u.data_ptr(), d.data_ptr(), m, n, C, H, W,
+          float(lam), float(eps), int(reg), out.data_ptr(), sp, _stream(view_spec))
+    return out
+
+
+def render(layer_spec: torch.Tensor, d: torch.Tensor, views: torch.Tensor, H: int, W: int,
+           out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Rendered spectra [V, C, H, W//2+1] (fdl_render).  ``views`` are [V, 5]
+    float rows (u, v, focus, radius, shape) or records from :func:`view_records`."""
+    n, C = layer_spec.shape[:2]
+    _check(layer_spec, torch.complex64, (n, C, H, W // 2 + 1), "layer_spec")
+    _check(d, torch.float32, (n,), "d")
+    if not views.is_cuda:
+        raise ValueError("views must be a device tensor")
+    rec = views if getattr(views, "_fdl_records", False) else view_records(views)
+    V = rec.shape[0]
+    if out is None:
+        out = torch.empty((V, C, H, W // 2 + 1), dtype=torch.complex64, device=layer_spec.device)
+    _check(out, torch.complex64, (V, C, H, W // 2 + 1), "out")
+    _call("fdl_render", layer_spec.data_ptr(), d.data_ptr(), n, C, H, W, rec.data_ptr(), V,
+          out.data_ptr(), _stream(layer_spec))
+    return out
+
+
+def calib_workspace_bytes(m: int, n: int, Q: int) -> int:
+    return int(lib().fdl_calib_workspace(m, n, Q))
+
+
+def calib_grad(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int, W: int,
+               lam: float, eps: float, reg: int, mode: int, freq_idx: Optional[torch.Tensor] = None,
+               out: Optional[Tuple[torch.Tensor, torch.Tensor, torch.Tensor]] = None,
+               ws: Optional[torch.Tensor] = None):
+    """(loss [1] f64, grad_u [m,2] f64, grad_d [n] f64) (fdl_calib_grad)."""
+    m, C = view_spec.shape[:2]
+    n = d.shape[0]
+    _check(view_spec, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
+    _check(u, torch.float32, (m, 2), "u")
+    _check(d, torch.float32, (n,), "d")
+    dev = view_spec.device
+    if freq_idx is not None:
+        _check(freq_idx, torch.int32, None, "freq_idx")
+        Q = freq_idx.numel()
+        fp = freq_idx.data_ptr()
+    else:
+        Q = H * (W // 2 + 1)
+        fp = 0
+    if out is None:
+        out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((m, 2), dtype=torch.float64, device=dev),
+               torch.empty(n, dtype=torch.float64, device=dev))
+    loss, gu, gd = out
+    need = calib_workspace_bytes(m, n, Q)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _call("fdl_calib_grad", view_spec.data_ptr(), u.data_ptr(), d.data_ptr(), m, n, C, H, W, float(lam),
+          float(eps), int(reg), int(mode), fp, Q, loss.data_ptr(), gu.data_ptr(), gd.data_ptr(),
+          ws.data_ptr(), ws.numel(), _stream(view_spec))
+    return loss, gu, gd
+
+
+def gd_step(u: torch.Tensor, d: torch.Tensor, grad_u: torch.Tensor, grad_d: torch.Tensor,
+            alpha: float = 0.2, eps_g: float = 1e-6) -> None:
+    """In-place normalised gradient step on u [m,2] f32 and d [n] f32 (fdl_gd_step)."""
+    m, n = u.shape[0], d.shape[0]
+    _check(u, torch.float32, (m, 2), "u")
+    _check(d, torch.float32, (n,), "d")
+    _check(grad_u, torch.float64, (m, 2), "grad_u")
+    _check(grad_d, torch.float64, (n,), "grad_d")
+    _call("fdl_gd_step", u.data_ptr(), d.data_ptr(), grad_u.data_ptr(), grad_d.data_ptr(), m, n,
+          float(alpha), float(eps_g), _stream(u))

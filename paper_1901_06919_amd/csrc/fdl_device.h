@@ -1,0 +1,151 @@
+// Device helpers shared by the FDL kernels: FP64 complex arithmetic, an
+// FP64 sin/cos of 2*pi*r, 16-lane team communication through DPP, and the
+// half-spectrum frequency mapping.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdl {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kTwoPi = 6.28318530717958647692;
+
+struct cd {
+  double re, im;
+};
+
+__device__ __forceinline__ cd cmake(double r, double i) { return cd{r, i}; }
+__device__ __forceinline__ cd cadd(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ cd csub(cd a, cd b) { return cd{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ cd cmul(cd a, cd b) {
+  return cd{fma(a.re, b.re, -a.im * b.im), fma(a.re, b.im, a.im * b.re)};
+}
+// conj(a) * b
+__device__ __forceinline__ cd cmulc(cd a, cd b) {
+  return cd{fma(a.re, b.re, a.im * b.im), fma(a.re, b.im, -a.im * b.re)};
+}
+__device__ __forceinline__ cd cscale(cd a, double s) { return cd{a.re * s, a.im * s}; }
+// acc += conj(a) * b
+__device__ __forceinline__ void cfma_conj(cd& acc, cd a, cd b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(-a.im, b.re, acc.im);
+}
+// acc -= a * conj(b)
+__device__ __forceinline__ void cfms_aconjb(cd& acc, cd a, cd b) {
+  acc.re = fma(-a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(-a.im, b.re, acc.im);
+  acc.im = fma(a.re, b.im, acc.im);
+}
+// acc += a * b
+__device__ __forceinline__ void cfma(cd& acc, cd a, cd b) {
+  acc.re = fma(a.re, b.re, acc.re);
+  acc.re = fma(-a.im, b.im, acc.re);
+  acc.im = fma(a.re, b.im, acc.im);
+  acc.im = fma(a.im, b.re, acc.im);
+}
+
+// sin(2 pi r), cos(2 pi r) to about 1 ulp of double for any |r| < 2^40.
+// Reduction: r - rint(r) in [-1/2, 1/2] (exact), then the nearest quarter
+// turn q/4 is removed (exact), leaving |x| = 2 pi |f| <= pi/4 where the
+// Taylor series of sin (through x^15) and cos (through x^16) are summed by
+// Horner's rule; truncation error < 5e-17.  The quarter turn is restored by
+// the identities sin(x + q pi/2), cos(x + q pi/2).
+__device__ __forceinline__ void sincos2pi(double r, double& s, double& c) {
+  r = r - rint(r);
+  const double q = rint(4.0 * r);
+  const double f = fma(-0.25, q, r);
+  const double x = kTwoPi * f;
+  const double x2 = x * x;
+  // sin(x) = x (1 - x^2/3! + x^4/5! - ... - x^14/15!)
+  double ps = -1.0 / 1307674368000.0;          // -1/15!
+  ps = fma(ps, x2, 1.0 / 6227020800.0);        // +1/13!
+  ps = fma(ps, x2, -1.0 / 39916800.0);         // -1/11!
+  ps = fma(ps, x2, 1.0 / 362880.0);            // +1/9!
+  ps = fma(ps, x2, -1.0 / 5040.0);             // -1/7!
+  ps = fma(ps, x2, 1.0 / 120.0);               // +1/5!
+  ps = fma(ps, x2, -1.0 / 6.0);                // -1/3!
+  const double sx = fma(x * x2, ps, x);
+  // cos(x) = 1 - x^2/2! + x^4/4! - ... + x^16/16!
+  double pc = 1.0 / 20922789888000.0;          // +1/16!
+  pc = fma(pc, x2, -1.0 / 87178291200.0);      // -1/14!
+  pc = fma(pc, x2, 1.0 / 479001600.0);         // +1/12!
+  pc = fma(pc, x2, -1.0 / 3628800.0);          // -1/10!
+  pc = fma(pc, x2, 1.0 / 40320.0);             // +1/8!
+  pc = fma(pc, x2, -1.0 / 720.0);              // -1/6!
+  pc = fma(pc, x2, 1.0 / 24.0);                // +1/4!
+  pc = fma(pc, x2, -0.5);                      // -1/2!
+  const double cx = fma(x2, pc, 1.0);
+  const int qi = ((int)q) & 3;
+  const double s1 = (qi & 1) ? cx : sx;
+  const double c1 = (qi & 1) ? sx : cx;
+  s = (qi & 2) ? -s1 : s1;
+  c = ((qi + 1) & 2) ? -c1 : c1;
+}
+
+__device__ __forceinline__ cd expi2pi(double r) {
+  cd z;
+  sincos2pi(r, z.im, z.re);
+  return z;
+}
+
+// ---- 16-lane team communication (one DPP row = one team) -------------------
+
+// Value of `v` in lane SRC of this lane's 16-lane row.
+template <int SRC>
+__device__ __forceinline__ double bcast16(double v) {
+  long long x = __double_as_longlong(v);
+  x = __builtin_amdgcn_update_dpp(x, x, 0x150 + SRC, 0xF, 0xF, false);
+  return __longlong_as_double(x);
+}
+template <int SRC>
+__device__ __forceinline__ cd bcast16(cd v) {
+  return cd{bcast16<SRC>(v.re), bcast16<SRC>(v.im)};
+}
+
+// Sum of `v` over the 16 lanes of the row, returned to every lane of the row.
+// Pair swap, quad swap, half-row mirror, row mirror: every lane adds the same
+// operands (in commuted order), so all 16 lanes hold bit-identical sums.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  long long x = __double_as_longlong(v);
+  x = __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(x);
+}
+__device__ __forceinline__ double allreduce16(double v) {
+  v += dpp_mov<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);  // row_half_mirror
+  v += dpp_mov<0x140>(v);  // row_mirror
+  return v;
+}
+
+// ---- frequency grid ---------------------------------------------------------
+
+// w_x = kx / W, w_y = ky / H folded to [-1/2, 1/2) (numpy fftfreq / rfftfreq).
+__device__ __forceinline__ void bin_freq(int f, int Wh, int H, int W, double& wx, double& wy) {
+  const int ky = f / Wh;
+  const int kx = f - ky * Wh;
+  const int kys = (ky < (H + 1) / 2) ? ky : ky - H;
+  wx = (double)kx / (double)W;
+  wy = (double)kys / (double)H;
+}
+
+// Spread consecutive block indices over the 8 XCDs so that each XCD works on
+// a contiguous range of bins (its own L2), instead of the round-robin
+// interleave of the hardware dispatcher.
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int kXcd = 8;
+  const int per = (nblocks + kXcd - 1) / kXcd;
+  const int xcd = bid % kXcd;
+  const int idx = bid / kXcd;
+  const int full = nblocks % kXcd == 0 ? kXcd : nblocks % kXcd;   // XCDs holding `per` blocks
+  // blocks of XCDs < full get `per`, the rest `per - 1`
+  const int base = xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1);
+  return base + idx;
+}
+
+}  // namespace fdl
