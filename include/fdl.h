@@ -92,21 +92,23 @@ const char* fdl_status_string(int code);
 int fdl_version(void);
 
 /* ---------------------------------------------------------------------------
- * Real 2D DFT (Sec. V-A "compute the discrete Fourier transform of each
- * image"; Sec. VII: only the Hermitian half is computed).
- *   img_dev  [batch][H][W] float32  ->  spec_dev [batch][H][W/2+1] complex64.
- * Unnormalised (numpy "backward" convention).  H and W must each be a
- * product of powers of 2 and 3, 4 <= W <= 4096, 2 <= H <= 4096, W even.
- * Returns FDL_ESHAPE otherwise.  In-place is not supported.
+ * Real 2D DFT (Sec. V-A: the layers are fitted to the DFT of each input
+ * image; Sec. VII: only the Hermitian half of each spectrum is computed).
+ *   img_dev  [batch][H][W] float32  ->  spec_dev [batch][H][W/2+1] complex64,
+ *   X[ky][kx] = sum_{y,x} img[y][x] exp(-2 pi i (ky y / H + kx x / W)), unnormalised.
+ * H and W/2 must be products of powers of 2 and 3 (128, 192, 256, 384, 512,
+ * ...); 1 <= H <= 4096, 2 <= W <= 8192, W even.  FDL_ESHAPE otherwise.
+ * The buffers must not overlap.
  * ------------------------------------------------------------------------- */
 int fdl_rfft2(const float* img_dev, fdl_c64* spec_dev, int batch, int H, int W, void* stream);
 
 /* Inverse of fdl_rfft2 with 1/(H W) normalisation:
  *   spec_dev [batch][H][W/2+1] complex64 -> img_dev [batch][H][W] float32.
  * The half spectrum is extended by Hermitian symmetry; the imaginary parts of
- * self-conjugate bins (DC/Nyquist rows of columns kx = 0 and kx = W/2) do not
- * contribute (numpy irfft2 semantics).  Same size rules as fdl_rfft2. */
-int fdl_irfft2(const fdl_c64* spec_dev, float* img_dev, int batch, int H, int W, void* stream);
+ * the self-conjugate bins of columns kx = 0 and kx = W/2 (after the column
+ * transform) do not contribute (numpy irfft2 semantics).  spec_dev is used as
+ * scratch: its contents are DESTROYED.  Same size rules as fdl_rfft2. */
+int fdl_irfft2(fdl_c64* spec_dev, float* img_dev, int batch, int H, int W, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Layer construction (Sec. V-A, Eq. LayerConstructProb and its closed form
@@ -122,18 +124,25 @@ int fdl_irfft2(const fdl_c64* spec_dev, float* img_dev, int batch, int H, int W,
  *
  *   view_spec_dev  [m][C][H][W/2+1] complex64  (b_j = spectrum of view j)
  *   u_dev          [m] fdl_f2                  view positions
- *   d_dev          [n] float32                 layer disparities (any values)
+ *   d_host         [n] float32, HOST memory     layer disparities (any values);
+ *                  read during the call and passed to the kernels by value.
+ *                  When they form an arithmetic progression up to float rounding
+ *                  the Gram matrix is built from n Toeplitz moment sums (exact to
+ *                  FP64; a bin whose positions make that expansion inexact,
+ *                  |2 pi eta p| > 3e-4, is counted in status_dev), otherwise from
+ *                  all n(n+1)/2 products.
  *   layer_spec_dev [n][C][H][W/2+1] complex64  output layer spectra
  *   status_dev     int32 device counter or NULL: incremented once per bin whose
  *                  Cholesky factorisation met a non-positive pivot (the pivot
  *                  is then replaced by a tiny positive value and the result is
- *                  not meaningful for that bin).
+ *                  not meaningful for that bin) or whose moment expansion was
+ *                  out of range (see d_host).
  * Requires 1 <= m <= 4096, 1 <= n <= FDL_MAX_LAYERS, 1 <= C <= FDL_MAX_CHANNELS,
  * H >= 1, W >= 2 even, lambda >= 0, eps >= 0 (eps > 0 needed for a solvable DC
  * bin with the view regulariser).  The solve is carried out in FP64 from the
  * complex64 inputs; outputs are rounded to complex64.
  * ------------------------------------------------------------------------- */
-int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_dev,
+int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_host,
                   int m, int n, int C, int H, int W, float lambda, float eps, int reg,
                   fdl_c64* layer_spec_dev, int32_t* status_dev, void* stream);
 

@@ -127,7 +127,8 @@ def rfft2(img: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor
 
 
 def irfft2(spec: torch.Tensor, H: int, W: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """[..., H, W//2+1] complex64 -> [..., H, W] float32 (fdl_irfft2)."""
+    """[..., H, W//2+1] complex64 -> [..., H, W] float32 (fdl_irfft2).  ``spec`` is
+    used as scratch and overwritten (pass a clone to keep it)."""
     batch = spec.numel() // (H * (W // 2 + 1))
     if out is None:
         out = torch.empty(spec.shape[:-1] + (W,), dtype=torch.float32, device=spec.device)
@@ -145,7 +146,9 @@ def construct(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int,
     n = d.shape[0]
     _check(view_spec, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
     _check(u, torch.float32, (m, 2), "u")
-    _check(d, torch.float32, (n,), "d")
+    if d.dtype != torch.float32 or d.dim() != 1:
+        raise TypeError("d must be a 1-D float32 tensor")
+    d_host = d.detach().to("cpu").contiguous()          # disparities travel by value
     if out is None:
         out = torch.empty((n, C, H, W // 2 + 1), dtype=torch.complex64, device=view_spec.device)
     _check(out, torch.complex64, (n, C, H, W // 2 + 1), "out")
@@ -153,7 +156,7 @@ def construct(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int,
     if status is not None:
         _check(status, torch.int32, (1,), "status")
         sp = status.data_ptr()
-    _call("fdl_construct", view_spec.data_ptr(), u.data_ptr(), d.data_ptr(), m, n, C, H, W,
+    _call("fdl_construct", view_spec.data_ptr(), u.data_ptr(), d_host.data_ptr(), m, n, C, H, W,
           float(lam), float(eps), int(reg), out.data_ptr(), sp, _stream(view_spec))
     return out
 

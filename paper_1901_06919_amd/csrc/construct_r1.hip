@@ -1,0 +1,31 @@
+// Plain construction kernels, one 16-lane team per half-spectrum bin,
+// instantiations for n <= 16 (R = 1 row slots per lane).
+#include "construct_team.h"
+
+namespace fdl {
+
+template <int R, int CT, bool TOEP>
+__global__ __launch_bounds__(256) void k_construct(ConstructParams P) {
+  __shared__ TeamLds s_team[16];
+  const int lane = threadIdx.x & 15;
+  const int team = threadIdx.x >> 4;
+  const int f = xcd_remap(blockIdx.x, gridDim.x) * 16 + team;
+  if (f >= P.F) return;
+  team_solve<R, CT, TOEP>(P, s_team[team], f, lane);
+}
+
+template <int CT, bool TOEP>
+static hipError_t go(const ConstructParams& P, hipStream_t s) {
+  const int blocks = (P.F + 15) / 16;
+  hipLaunchKernelGGL((k_construct<1, CT, TOEP>), dim3(blocks), dim3(256), 0, s, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_construct_r1(const ConstructParams& P, hipStream_t s) {
+  const bool t = P.toeplitz != 0;
+  if (P.C == 1) return t ? go<1, true>(P, s) : go<1, false>(P, s);
+  if (P.C <= 3) return t ? go<3, true>(P, s) : go<3, false>(P, s);
+  return t ? go<4, true>(P, s) : go<4, false>(P, s);
+}
+
+}  // namespace fdl

@@ -6,15 +6,19 @@
 
 namespace fdl {
 
+// One light field for the construction kernels.  The disparities travel by
+// value (n <= 32), together with the host's classification of them.
 struct ConstructParams {
   const float2* view_spec;   // [m][C][F]
   const float2* u;           // [m]
-  const float* d;            // [n]
   float2* layer_spec;        // [n][C][F]
   int* status;               // device counter or null
   int m, n, C, H, W, Wh, F;
   double lambda, eps;
   int reg;
+  int toeplitz;              // 1: d is an arithmetic progression up to rounding
+  double eta_max;            // max_k1<k2 |(d_k2-d_k1) - (d_{k2-k1}-d_0)|
+  double d[32];
 };
 
 struct RenderParams {
@@ -25,7 +29,27 @@ struct RenderParams {
   int n, C, H, W, Wh, F, V;
 };
 
-hipError_t launch_construct(const ConstructParams& P, hipStream_t s);
+hipError_t launch_construct_r1(const ConstructParams& P, hipStream_t s);   // n <= 16
+hipError_t launch_construct_r2(const ConstructParams& P, hipStream_t s);   // n <= 32
 hipError_t launch_render(const RenderParams& P, hipStream_t s);
+
+// Mixed-radix (4, 2, 3) plan for one FFT length.
+struct FftPlan {
+  int N;
+  int nst;
+  int radix[24];
+};
+
+struct FftParams {
+  float* real;      // [batch][H][W]
+  float2* cplx;     // [batch][H][W/2+1]
+  int batch, H, W;
+  FftPlan row_plan; // length W/2
+  FftPlan col_plan; // length H
+  int col_tc;       // columns per block in the column pass
+};
+
+hipError_t launch_rfft2(const FftParams& P, hipStream_t s);
+hipError_t launch_irfft2(const FftParams& P, hipStream_t s);
 
 }  // namespace fdl

@@ -1,0 +1,247 @@
+// Real 2D DFT and its inverse for image sizes 2^a 3^b (Sec. V-A: the layer
+// model works on the DFT of each input image; Sec. VII: only the Hermitian
+// half spectrum [H][W/2+1] is computed and stored).
+//
+// Forward: (1) rows: each real row of length W is packed as W/2 complex
+//   values z[n] = x[2n] + i x[2n+1], transformed by an LDS Stockham FFT and
+//   split into the half spectrum X[k] = E[k] + e^{-2 pi i k/W} O[k],
+//   E = (Z[k] + conj Z[N-k])/2, O = -i (Z[k] - conj Z[N-k])/2, k = 0..W/2;
+//   (2) columns: complex FFT of length H of every column kx, in place.
+// Inverse: (1) columns: inverse complex FFT in place (the input buffer is
+//   scratch); (2) rows: Z[k] = E[k] + i O[k] with E = (X[k] + conj X[N-k])/2,
+//   O = e^{+2 pi i k/W} (X[k] - conj X[N-k])/2 (imaginary parts of X[0], X[N]
+//   dropped, numpy semantics), inverse FFT of length W/2, unpacked to 2 reals.
+//   Normalisation 1/(H W).
+//
+// The in-LDS transform is the Stockham autosort formulation (Govindaraju et
+// al., "High performance discrete Fourier transforms on graphics processors",
+// SC 2008) with radix-4, radix-2 and radix-3 butterflies; twiddles are
+// evaluated by the transcendental unit in revolutions after exact range
+// reduction.  FP32 throughout.
+#include "fdl_device.h"
+#include "fdl_internal.h"
+
+namespace fdl {
+
+__device__ __forceinline__ float2 f2add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 f2sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 f2mul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ float2 f2conj(float2 a) { return make_float2(a.x, -a.y); }
+__device__ __forceinline__ float2 f2scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// multiply by -i (forward) or +i (inverse)
+template <bool INV>
+__device__ __forceinline__ float2 rot90(float2 a) {
+  return INV ? make_float2(-a.y, a.x) : make_float2(a.y, -a.x);
+}
+// exp(2 pi i r), r in revolutions
+__device__ __forceinline__ float2 twiddle(float r) {
+  r = r - rintf(r);
+  return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
+}
+
+// One Stockham stage of radix R over a length-N sequence held in LDS.
+template <bool INV>
+__device__ __forceinline__ void stockham_stage(const float2* __restrict__ in, float2* __restrict__ out, int N, int Ns,
+                                               int R, int t, int G) {
+  const int nb = N / R;
+  const float sgn = INV ? 1.0f : -1.0f;
+  for (int j = t; j < nb; j += G) {
+    const int k = j % Ns;
+    float2 v[4];
+    for (int r = 0; r < R; ++r) v[r] = in[j + r * nb];
+    if (Ns > 1) {
+      const float a = sgn * (float)k / (float)(Ns * R);
+      for (int r = 1; r < R; ++r) v[r] = f2mul(v[r], twiddle(a * (float)r));
+    }
+    if (R == 4) {
+      const float2 a0 = f2add(v[0], v[2]), a1 = f2sub(v[0], v[2]);
+      const float2 a2 = f2add(v[1], v[3]), a3 = rot90<INV>(f2sub(v[1], v[3]));
+      v[0] = f2add(a0, a2);
+      v[2] = f2sub(a0, a2);
+      v[1] = f2add(a1, a3);
+      v[3] = f2sub(a1, a3);
+    } else if (R == 2) {
+      const float2 a0 = v[0];
+      v[0] = f2add(a0, v[1]);
+      v[1] = f2sub(a0, v[1]);
+    } else {   // R == 3
+      const float2 t1 = f2add(v[1], v[2]);
+      const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+      const float2 s = f2scale(rot90<INV>(f2sub(v[1], v[2])), 0.86602540378443864676f);
+      v[0] = f2add(v[0], t1);
+      v[1] = f2add(t2, s);
+      v[2] = f2sub(t2, s);
+    }
+    const int base = (j / Ns) * Ns * R + k;
+    for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
+  }
+}
+
+// Runs every stage; returns the buffer that holds the result.  All G*groups
+// threads of the block call it together (block barriers inside).
+template <bool INV>
+__device__ __forceinline__ float2* lds_fft(float2* b0, float2* b1, const FftPlan& plan, int t, int G) {
+  int Ns = 1;
+  float2* in = b0;
+  float2* out = b1;
+  for (int s = 0; s < plan.nst; ++s) {
+    const int R = plan.radix[s];
+    stockham_stage<INV>(in, out, plan.N, Ns, R, t, G);
+    __syncthreads();
+    Ns *= R;
+    float2* tmp = in;
+    in = out;
+    out = tmp;
+  }
+  return in;
+}
+
+// ---- forward rows: real rows -> half spectra --------------------------------
+__global__ __launch_bounds__(256) void k_rfft_rows(const float* __restrict__ img, float2* __restrict__ out,
+                                                   int nrows, int W, FftPlan plan, int G) {
+  extern __shared__ float2 lds[];
+  const int N = plan.N;              // W / 2
+  const int rpb = blockDim.x / G;
+  const int lr = threadIdx.x / G;
+  const int t = threadIdx.x - lr * G;
+  const int row = blockIdx.x * rpb + lr;
+  float2* b0 = lds + (size_t)lr * 2 * N;
+  float2* b1 = b0 + N;
+  const bool live = row < nrows;
+  if (live) {
+    const float2* src = reinterpret_cast<const float2*>(img + (size_t)row * W);
+    for (int i = t; i < N; i += G) b0[i] = src[i];
+  }
+  __syncthreads();
+  const float2* Z = lds_fft<false>(b0, b1, plan, t, G);
+  if (live) {
+    float2* dst = out + (size_t)row * (N + 1);
+    const float invW = 1.0f / (float)W;
+    for (int k = t; k <= N; k += G) {
+      const float2 zk = Z[k == N ? 0 : k];
+      const float2 zn = f2conj(Z[k == 0 ? 0 : N - k]);
+      const float2 E = f2scale(f2add(zk, zn), 0.5f);
+      const float2 O = f2scale(rot90<false>(f2sub(zk, zn)), 0.5f);
+      dst[k] = f2add(E, f2mul(twiddle(-(float)k * invW), O));
+    }
+  }
+}
+
+// ---- inverse rows: half spectra -> real rows ---------------------------------
+__global__ __launch_bounds__(256) void k_irfft_rows(const float2* __restrict__ spec, float* __restrict__ img,
+                                                    int nrows, int W, FftPlan plan, int G, float scale) {
+  extern __shared__ float2 lds[];
+  const int N = plan.N;
+  const int rpb = blockDim.x / G;
+  const int lr = threadIdx.x / G;
+  const int t = threadIdx.x - lr * G;
+  const int row = blockIdx.x * rpb + lr;
+  float2* b0 = lds + (size_t)lr * 2 * N;
+  float2* b1 = b0 + N;
+  const bool live = row < nrows;
+  if (live) {
+    const float2* src = spec + (size_t)row * (N + 1);
+    const float invW = 1.0f / (float)W;
+    for (int k = t; k < N; k += G) {
+      float2 xk = src[k];
+      float2 xn = src[N - k];
+      if (k == 0) { xk.y = 0.0f; xn.y = 0.0f; }   // self-conjugate bins are real
+      xn = f2conj(xn);
+      const float2 E = f2scale(f2add(xk, xn), 0.5f);
+      const float2 O = f2scale(f2mul(twiddle((float)k * invW), f2sub(xk, xn)), 0.5f);
+      b0[k] = f2add(E, rot90<true>(O));
+    }
+  }
+  __syncthreads();
+  const float2* z = lds_fft<true>(b0, b1, plan, t, G);
+  if (live) {
+    float2* dst = reinterpret_cast<float2*>(img + (size_t)row * W);
+    for (int i = t; i < N; i += G) dst[i] = f2scale(z[i], scale);
+  }
+}
+
+// ---- columns: complex FFT of length H over a tile of TC columns, in place ----
+template <bool INV>
+__global__ __launch_bounds__(256) void k_fft_cols(float2* __restrict__ data, int batch, int H, int Wh, int tiles,
+                                                  FftPlan plan, int G, int TC) {
+  extern __shared__ float2 lds[];
+  const int img = blockIdx.x / tiles;
+  const int c0 = (blockIdx.x - img * tiles) * TC;
+  const int lc = threadIdx.x / G;
+  const int t = threadIdx.x - lc * G;
+  float2* base = data + (size_t)img * H * Wh;
+  // transpose-load: lds[c][y]
+  for (int q = threadIdx.x; q < H * TC; q += blockDim.x) {
+    const int y = q / TC, c = q - y * TC;
+    if (c0 + c < Wh) lds[(size_t)c * 2 * H + y] = base[(size_t)y * Wh + c0 + c];
+  }
+  __syncthreads();
+  float2* b0 = lds + (size_t)lc * 2 * H;
+  const float2* r = lds_fft<INV>(b0, b0 + H, plan, t, G);
+  const size_t roff = (size_t)(r - b0);   // 0 or H: same for every column
+  for (int q = threadIdx.x; q < H * TC; q += blockDim.x) {
+    const int y = q / TC, c = q - y * TC;
+    if (c0 + c < Wh) base[(size_t)y * Wh + c0 + c] = lds[(size_t)c * 2 * H + roff + y];
+  }
+}
+
+static int pick_threads(int N) {
+  int g = 1;
+  while (g * 2 <= 256 && g * 2 * 4 <= N) g *= 2;   // about N/4 butterflies per stage
+  return g;
+}
+
+hipError_t launch_rfft2(const FftParams& P, hipStream_t s) {
+  const int N = P.W / 2;
+  // rows
+  {
+    const int G = pick_threads(N);
+    const int rpb = 256 / G;
+    const int nrows = P.batch * P.H;
+    const size_t lds = (size_t)rpb * 2 * N * sizeof(float2);
+    hipLaunchKernelGGL(k_rfft_rows, dim3((nrows + rpb - 1) / rpb), dim3(rpb * G), lds, s, P.real, P.cplx, nrows,
+                       P.W, P.row_plan, G);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  // columns
+  {
+    const int H = P.H, Wh = N + 1;
+    const int TC = P.col_tc;
+    const int G = 256 / TC;
+    const int tiles = (Wh + TC - 1) / TC;
+    const size_t lds = (size_t)TC * 2 * H * sizeof(float2);
+    hipLaunchKernelGGL(k_fft_cols<false>, dim3(P.batch * tiles), dim3(TC * G), lds, s, P.cplx, P.batch, H, Wh,
+                       tiles, P.col_plan, G, TC);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_irfft2(const FftParams& P, hipStream_t s) {
+  const int N = P.W / 2;
+  {
+    const int H = P.H, Wh = N + 1;
+    const int TC = P.col_tc;
+    const int G = 256 / TC;
+    const int tiles = (Wh + TC - 1) / TC;
+    const size_t lds = (size_t)TC * 2 * H * sizeof(float2);
+    hipLaunchKernelGGL(k_fft_cols<true>, dim3(P.batch * tiles), dim3(TC * G), lds, s, P.cplx, P.batch, H, Wh,
+                       tiles, P.col_plan, G, TC);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  {
+    const int G = pick_threads(N);
+    const int rpb = 256 / G;
+    const int nrows = P.batch * P.H;
+    const size_t lds = (size_t)rpb * 2 * N * sizeof(float2);
+    const float scale = 1.0f / ((float)P.H * (float)N);   // E, O above already carry the 1/2
+    hipLaunchKernelGGL(k_irfft_rows, dim3((nrows + rpb - 1) / rpb), dim3(rpb * G), lds, s, P.cplx, P.real, nrows,
+                       P.W, P.row_plan, G, scale);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace fdl

@@ -32,6 +32,42 @@ void trace(const char* what, int a, int b, int c, int d) {
   if (std::getenv("FDL_TRACE")) std::fprintf(stderr, "fdl: %s %d %d %d %d\n", what, a, b, c, d);
 }
 
+// Classify the disparities: an arithmetic progression up to float rounding
+// lets the kernels build A^H A from n Toeplitz moment sums.
+void classify_disparities(const float* d, int n, fdl::ConstructParams& P) {
+  double dmax = 0.0, eta = 0.0;
+  for (int k = 0; k < 32; ++k) P.d[k] = k < n ? (double)d[k] : 0.0;
+  for (int k = 0; k < n; ++k) dmax = std::fmax(dmax, std::fabs(P.d[k]));
+  for (int k1 = 0; k1 < n; ++k1)
+    for (int k2 = k1 + 1; k2 < n; ++k2)
+      eta = std::fmax(eta, std::fabs((P.d[k2] - P.d[k1]) - (P.d[k2 - k1] - P.d[0])));
+  P.eta_max = eta;
+  P.toeplitz = eta <= 1e-5 * (1.0 + dmax) ? 1 : 0;
+}
+
+// Factor N = 4^a 2^b 3^c into Stockham radices; false if N has another factor.
+bool make_plan(int N, fdl::FftPlan& plan) {
+  plan.N = N;
+  plan.nst = 0;
+  int v = N;
+  while (v % 4 == 0 && plan.nst < 24) { plan.radix[plan.nst++] = 4; v /= 4; }
+  while (v % 2 == 0 && plan.nst < 24) { plan.radix[plan.nst++] = 2; v /= 2; }
+  while (v % 3 == 0 && plan.nst < 24) { plan.radix[plan.nst++] = 3; v /= 3; }
+  return v == 1;
+}
+
+int fft_params(int batch, int H, int W, fdl::FftParams& P) {
+  if (batch < 1 || H < 1 || H > 4096 || W < 2 || W > 8192 || (W & 1)) return FDL_ESHAPE;
+  if (!make_plan(W / 2, P.row_plan) || !make_plan(H, P.col_plan)) return FDL_ESHAPE;
+  P.batch = batch;
+  P.H = H;
+  P.W = W;
+  int tc = 16;
+  while (tc > 1 && (size_t)tc * 2 * H * 8 > 65536) tc /= 2;
+  P.col_tc = tc;
+  return FDL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -51,26 +87,29 @@ const char* fdl_status_string(int code) {
 
 int fdl_version(void) { return 10000; }
 
-int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_dev, int m, int n, int C,
+int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_host, int m, int n, int C,
                   int H, int W, float lambda, float eps, int reg, fdl_c64* layer_spec_dev, int32_t* status_dev,
                   void* stream) {
-  if (!view_spec_dev || !u_dev || !d_dev || !layer_spec_dev) return FDL_EINVAL;
+  if (!view_spec_dev || !u_dev || !d_host || !layer_spec_dev) return FDL_EINVAL;
   if (!(std::isfinite(lambda) && lambda >= 0.f) || !(std::isfinite(eps) && eps >= 0.f)) return FDL_EINVAL;
   if (reg < FDL_REG_VIEW2 || reg > FDL_REG_L2) return FDL_EINVAL;
   if (m < 1 || m > 4096 || n < 1 || n > FDL_MAX_LAYERS || C < 1 || C > FDL_MAX_CHANNELS) return FDL_ESHAPE;
   if (H < 1 || W < 2 || (W & 1)) return FDL_ESHAPE;
+  for (int k = 0; k < n; ++k)
+    if (!std::isfinite(d_host[k])) return FDL_EINVAL;
   const long long F = (long long)H * (W / 2 + 1);
   if (F > (1LL << 30)) return FDL_ESHAPE;
   fdl::ConstructParams P;
   P.view_spec = reinterpret_cast<const float2*>(view_spec_dev);
   P.u = reinterpret_cast<const float2*>(u_dev);
-  P.d = d_dev;
   P.layer_spec = reinterpret_cast<float2*>(layer_spec_dev);
   P.status = status_dev;
   P.m = m; P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F;
   P.lambda = (double)lambda; P.eps = (double)eps; P.reg = reg;
+  classify_disparities(d_host, n, P);
   trace("construct m n C F", m, n, C, (int)F);
-  return map_hip(fdl::launch_construct(P, reinterpret_cast<hipStream_t>(stream)));
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  return map_hip(n <= 16 ? fdl::launch_construct_r1(P, s) : fdl::launch_construct_r2(P, s));
 }
 
 int fdl_render(const fdl_c64* layer_spec_dev, const float* d_dev, int n, int C, int H, int W,
@@ -88,6 +127,28 @@ int fdl_render(const fdl_c64* layer_spec_dev, const float* d_dev, int n, int C, 
   P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F; P.V = V;
   trace("render n C F V", n, C, (int)F, V);
   return map_hip(fdl::launch_render(P, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int fdl_rfft2(const float* img_dev, fdl_c64* spec_dev, int batch, int H, int W, void* stream) {
+  if (!img_dev || !spec_dev) return FDL_EINVAL;
+  fdl::FftParams P;
+  const int e = fft_params(batch, H, W, P);
+  if (e != FDL_OK) return e;
+  P.real = const_cast<float*>(img_dev);
+  P.cplx = reinterpret_cast<float2*>(spec_dev);
+  trace("rfft2 batch H W", batch, H, W, 0);
+  return map_hip(fdl::launch_rfft2(P, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int fdl_irfft2(fdl_c64* spec_dev, float* img_dev, int batch, int H, int W, void* stream) {
+  if (!img_dev || !spec_dev) return FDL_EINVAL;
+  fdl::FftParams P;
+  const int e = fft_params(batch, H, W, P);
+  if (e != FDL_OK) return e;
+  P.real = img_dev;
+  P.cplx = reinterpret_cast<float2*>(spec_dev);
+  trace("irfft2 batch H W", batch, H, W, 0);
+  return map_hip(fdl::launch_irfft2(P, reinterpret_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"
