@@ -167,14 +167,14 @@ int fdl_render(const fdl_c64* layer_spec_dev, const float* d_dev, int n, int C, 
  * (flat half-spectrum indices, or all F = H(W/2+1) bins when freq_idx_dev is
  * NULL), with orthonormal spectra b = view_spec / sqrt(H W):
  *
- * FDL_LOSS_FIT (Eq. CalibrationProb):
- *   E = (1/Q) sum_q [ ||A x_q - b_q||^2 + lambda ||Gamma x_q||^2 + eps ||x_q||^2 ],
+ * FDL_LOSS_FIT (Eq. CalibrationProb, summed over the sampled bins):
+ *   E = sum_q [ ||A x_q - b_q||^2 + lambda ||Gamma x_q||^2 + eps ||x_q||^2 ],
  *   x_q the minimiser; gradient by Eqs. gradP / gradD generalised to 2D:
  *   G_jk = 4 pi Im(conj(x_k) conj(A_jk) r_j), r = A x - b,
- *   grad u_j = (1/Q) sum_q sum_k d_k G_jk w_q, grad d_k = (1/Q) sum_q sum_j G_jk <u_j, w_q>.
+ *   grad u_j = sum_q sum_k d_k G_jk w_q, grad d_k = sum_q sum_j G_jk <u_j, w_q>.
  *   Exact when the regulariser does not depend on d (FDL_REG_LAYER2, FDL_REG_L2).
  * FDL_LOSS_LOO (leave-one-out view prediction):
- *   E = (1/Q) sum_q sum_j |r_j / (1 - h_jj)|^2, r = b - A x, h_jj = a_j M^-1 a_j^H,
+ *   E = sum_q sum_j |r_j / (1 - h_jj)|^2, r = b - A x, h_jj = a_j M^-1 a_j^H,
  *   which equals the error of predicting view j from the layers fitted without
  *   it; the gradient back-propagates through M^-1 (hand-written adjoint).
  *
@@ -182,7 +182,13 @@ int fdl_render(const fdl_c64* layer_spec_dev, const float* d_dev, int n, int C, 
  *   ws_dev / ws_bytes: device workspace of at least fdl_calib_workspace(m, n, Q)
  *   bytes (per-block partial sums; reduced deterministically on the device).
  * Requires 1 <= m <= 256, 1 <= n <= FDL_MAX_LAYERS, 1 <= C <= FDL_MAX_CHANNELS,
- * Q >= 1 when freq_idx_dev != NULL, every index in [0, F).
+ * Q >= 1 when freq_idx_dev != NULL, every index in [0, F) (not checked: an
+ * index outside [0, F) reads outside view_spec_dev), and the per-bin system
+ * must fit one block's 64 KiB of LDS: 8 * (2mn + 2n^2 + 4mC + 2nC + m + mn + 64)
+ * bytes for FIT, plus 8 * (2nm + 4mC + 2nC + m + 2n^2) for LOO (FDL_ESHAPE
+ * otherwise; m = 49, n = 16, C = 1 needs 44 KiB in LOO mode).
+ * With FDL_REG_VIEW2 the regulariser depends on d; its derivative is not
+ * included (the paper pairs calibration with the layer regulariser).
  * ------------------------------------------------------------------------- */
 size_t fdl_calib_workspace(int m, int n, int Q);
 int fdl_calib_grad(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_dev,

@@ -30,8 +30,10 @@ Readings of the paper used here (each stated where it is used):
 * R2  2D second-order view regulariser: diag(|w|^4 d_k^4) (Eq. 2ndOrderView).
 * R3  apertures have unit integral, so psi_hat(0) = 1; disk of radius rho,
       square of half-side rho, rho = 0 is a pinhole (Sec. VI, scale factor f).
-* R4  calibration loss uses orthonormal spectra (DFT / sqrt(HW)) and the
-      mean over the frequency subset; the update uses ||grad||^2 as printed.
+* R4  calibration loss uses orthonormal spectra (DFT / sqrt(HW)) and, as in
+      Eq. CalibrationProb, the SUM over the sampled frequencies (the
+      stochastic subset replaces the full sum); the update uses ||grad||^2
+      as printed.
 """
 from __future__ import annotations
 
@@ -257,12 +259,12 @@ def calib_fit_loss_grad(view_spec: np.ndarray, u: np.ndarray, d: np.ndarray, H: 
                         lam: float, eps: float, reg: int, freq_index: np.ndarray):
     """Paper-mode calibration objective and its gradient.
 
-    E(u, d) = (1/|S|) sum_{q in S} min_x ||A_q x - b_q||^2 + lam ||Gamma x||^2 + eps ||x||^2
+    E(u, d) = sum_{q in S} min_x ||A_q x - b_q||^2 + lam ||Gamma x||^2 + eps ||x||^2
     (Eq. CalibrationProb with R1, R4).  With x_q at the minimum, the gradient
     is that of the data term alone (the regulariser does not depend on u, d):
     G_jk(q) = 4 pi Im( conj(x_k) conj(A_jk) r_j ),  r = A x - b   (Eq. gradP),
-    grad u_j = (1/|S|) sum_q sum_k d_k G_jk(q) w_q          (2-vector, Eq. gradD generalised),
-    grad d_k = (1/|S|) sum_q sum_j G_jk(q) <u_j, w_q>.
+    grad u_j = sum_q sum_k d_k G_jk(q) w_q          (2-vector, Eq. gradD generalised),
+    grad d_k = sum_q sum_j G_jk(q) <u_j, w_q>.
     Returns (loss, grad_u [m,2], grad_d [n]) as float64.
     """
     u = np.asarray(u, dtype=np.float64)
@@ -277,21 +279,21 @@ def calib_fit_loss_grad(view_spec: np.ndarray, u: np.ndarray, d: np.ndarray, H: 
     n = d.shape[0]
     Rfull = lam * R + eps * np.eye(n)[None]
     loss = (np.sum(np.abs(r) ** 2)
-            + np.real(np.einsum("qkc,qkl,qlc->", np.conj(x), Rfull, x))) / Q
+            + np.real(np.einsum("qkc,qkl,qlc->", np.conj(x), Rfull, x)))
     # G[q, j, k] = 4 pi Im( sum_c conj(x_kc) conj(A_jk) r_jc )
     G = 4.0 * math.pi * np.imag(np.conj(A) * np.einsum("qkc,qjc->qjk", np.conj(x), r))
     grad_u = np.zeros((u.shape[0], 2))
-    grad_u[:, 0] = np.einsum("qjk,k,q->j", G, d, wx) / Q
-    grad_u[:, 1] = np.einsum("qjk,k,q->j", G, d, wy) / Q
+    grad_u[:, 0] = np.einsum("qjk,k,q->j", G, d, wx)
+    grad_u[:, 1] = np.einsum("qjk,k,q->j", G, d, wy)
     p = wx[:, None] * u[None, :, 0] + wy[:, None] * u[None, :, 1]          # [Q, m]
-    grad_d = np.einsum("qjk,qj->k", G, p) / Q
+    grad_d = np.einsum("qjk,qj->k", G, p)
     return float(loss), grad_u, grad_d
 
 
 def calib_loo_loss(view_spec: np.ndarray, u: np.ndarray, d: np.ndarray, H: int, W: int,
                    lam: float, eps: float, reg: int, freq_index: np.ndarray) -> float:
     """Leave-one-out view-prediction loss, straight from its definition:
-    E = (1/|S|) sum_q sum_j sum_c | b_jc - a_j x^(-j)_c |^2, where x^(-j)
+    E = sum_{q in S} sum_j sum_c | b_jc - a_j x^(-j)_c |^2, where x^(-j)
     solves the same regularised problem (Eq. LayerConstructProb) with view j
     removed.  One explicit refit per view and frequency."""
     u = np.asarray(u, dtype=np.float64)
@@ -308,7 +310,7 @@ def calib_loo_loss(view_spec: np.ndarray, u: np.ndarray, d: np.ndarray, H: int, 
         x = np.linalg.solve(M, np.conj(np.swapaxes(Aj, -1, -2)) @ b[:, keep, :])
         pred = np.einsum("qk,qkc->qc", A[:, j, :], x)
         total += np.sum(np.abs(b[:, j, :] - pred) ** 2)
-    return float(total / Q)
+    return float(total)
 
 
 def calib_loo_loss_grad(view_spec: np.ndarray, u: np.ndarray, d: np.ndarray, H: int, W: int,
@@ -343,7 +345,7 @@ def calib_loo_loss_grad(view_spec: np.ndarray, u: np.ndarray, d: np.ndarray, H: 
         x = torch.linalg.solve(M, Ajh @ b[:, keep, :])
         pred = torch.einsum("qk,qkc->qc", A[:, j, :], x)
         total = total + torch.sum(torch.abs(b[:, j, :] - pred) ** 2)
-    loss = total / Q
+    loss = total
     loss.backward()
     return float(loss.detach()), tu.grad.numpy().copy(), td.grad.numpy().copy()
 

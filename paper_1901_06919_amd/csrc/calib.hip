@@ -1,0 +1,367 @@
+// Calibration objective and gradient with respect to view positions u_j and
+// disparities d_k (Sec. V-B, Eqs. CalibrationProb, gradD, gradP), plus the
+// leave-one-out (LOO) view-prediction loss with its exact adjoint, and the
+// normalised gradient step of Sec. V-B.
+//
+// One wave (one block of 64 threads) handles one sampled bin at a time
+// (grid-stride over the Q bins); the small dense algebra of the bin lives in
+// LDS in FP64 and the 64 lanes split its loops.  Per bin:
+//   A_jk = exp(2 pi i d_k p_j), M = A^H A + lambda Gamma^H Gamma + eps I = L L^H,
+//   x = M^-1 A^H b (b orthonormal: DFT / sqrt(HW)).
+// FIT:  r = A x - b, E_q = ||r||^2 + x^H (lambda G + eps I) x,
+//       T_jk = dE_q/dtheta_jk = 4 pi Im(conj(x_k) conj(A_jk) r_j) (Eq. gradP; the
+//       regulariser is frozen at the minimiser, envelope theorem).
+// LOO:  r = b - A x, h_j = a_j M^-1 a_j^H = ||L^-1 a_j^H||^2 (PRESS identity),
+//       E_q = sum_j |r_j|^2 / (1 - h_j)^2.  With P = L^-1 A^H, G = L^-H P = M^-1 A^H,
+//       H = A G, w = r/(1-h)^2, gam = 2|r|^2/(1-h)^3, y = G w, v = w - A y,
+//       Wm = A^T diag(gam) G^T, the Wirtinger derivative dE/dA is
+//       Psi_jk = sum_c[-conj(v_jc) x_kc - conj(r_jc) y_kc] + gam_j G_kj - (G^T Wm)_jk
+//       and T_jk = -4 pi Im(Psi_jk A_jk).
+// Both: grad u_j += sum_k d_k T_jk w_q,  grad d_k += sum_j T_jk p_j  (theta_jk =
+//       d_k <u_j, w>), summed over the Q sampled bins (Eq. CalibrationProb sums
+//       over the frequency components; the sampled subset replaces the full sum).
+// Per-block partial sums are reduced in a fixed order by a second kernel, so
+// the result is bitwise reproducible.
+#include "fdl_device.h"
+#include "fdl_internal.h"
+
+namespace fdl {
+
+struct CalibLayout {   // offsets (in doubles) into the dynamic LDS of one block
+  int A, L, b, x, r, p, T, P, w, y, v, gam, Wm, red;
+  int total;
+};
+
+__host__ __device__ inline CalibLayout calib_layout(int m, int n, int C, int mode) {
+  CalibLayout o;
+  int at = 0;
+  o.A = at; at += 2 * m * n;
+  o.L = at; at += 2 * n * n;
+  o.b = at; at += 2 * m * C;
+  o.x = at; at += 2 * n * C;
+  o.r = at; at += 2 * m * C;
+  o.p = at; at += m;
+  o.T = at; at += m * n;
+  if (mode == 1) {
+    o.P = at; at += 2 * n * m;
+    o.w = at; at += 2 * m * C;
+    o.y = at; at += 2 * n * C;
+    o.v = at; at += 2 * m * C;
+    o.gam = at; at += m;
+    o.Wm = at; at += 2 * n * n;
+  } else {
+    o.P = o.w = o.y = o.v = o.gam = o.Wm = 0;
+  }
+  o.red = at; at += 64;
+  o.total = at;
+  return o;
+}
+
+size_t calib_lds_bytes(int m, int n, int C, int mode) { return (size_t)calib_layout(m, n, C, mode).total * 8; }
+
+__device__ __forceinline__ cd ldc(const double* s, int i) { return cd{s[2 * i], s[2 * i + 1]}; }
+__device__ __forceinline__ void stc(double* s, int i, cd v) { s[2 * i] = v.re; s[2 * i + 1] = v.im; }
+
+__device__ __forceinline__ double reg_entry(int reg, int i, int k, int n, double lambda, double w4, double di) {
+  if (reg == 0) return (i == k) ? lambda * w4 * di * di * di * di : 0.0;
+  if (reg == 1) {
+    double s = 0.0;
+    for (int p = i - 1; p <= i + 1; ++p) {
+      if (p < 0 || p >= n) continue;
+      const int a = p - i, b = p - k;
+      if (b < -1 || b > 1) continue;
+      s += (a == 0 ? -2.0 : 1.0) * (b == 0 ? -2.0 : 1.0);
+    }
+    return lambda * s;
+  }
+  return (i == k) ? lambda : 0.0;
+}
+
+__global__ __launch_bounds__(64) void k_calib(CalibParams P) {
+  extern __shared__ double sm[];
+  const int m = P.m, n = P.n, C = P.C;
+  const CalibLayout o = calib_layout(m, n, C, P.mode);
+  double* A = sm + o.A;
+  double* L = sm + o.L;
+  double* b = sm + o.b;
+  double* x = sm + o.x;
+  double* r = sm + o.r;
+  double* pj = sm + o.p;
+  double* T = sm + o.T;
+  const int t = threadIdx.x;
+  const size_t F = (size_t)P.F;
+
+  double gu[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};   // views j = t + 64 s
+  double gd = 0.0;                                       // layer k = t
+  double loss = 0.0;
+
+  for (int q = blockIdx.x; q < P.Q; q += gridDim.x) {
+    const int f = P.freq_idx ? P.freq_idx[q] : q;
+    double wx, wy;
+    bin_freq(f, P.Wh, P.H, P.W, wx, wy);
+    const double w2 = wx * wx + wy * wy, w4 = w2 * w2;
+
+    for (int j = t; j < m; j += 64) {
+      const float2 uj = P.u[j];
+      pj[j] = (double)uj.x * wx + (double)uj.y * wy;
+    }
+    for (int i = t; i < m * C; i += 64) {
+      const float2 v = P.view_spec[(size_t)i * F + f];
+      stc(b, i, cd{(double)v.x * P.bscale, (double)v.y * P.bscale});
+    }
+    __syncthreads();
+    for (int i = t; i < m * n; i += 64) {
+      const int j = i / n, k = i - j * n;
+      stc(A, i, expi2pi((double)P.d[k] * pj[j]));
+    }
+    __syncthreads();
+    // normal matrix (lower triangle, full storage) and right-hand sides
+    for (int i = t; i < n * n; i += 64) {
+      const int k1 = i / n, k2 = i - k1 * n;
+      if (k2 > k1) continue;
+      cd s = cd{0.0, 0.0};
+      for (int j = 0; j < m; ++j) cfma_conj(s, ldc(A, j * n + k1), ldc(A, j * n + k2));
+      s.re += reg_entry(P.reg, k1, k2, n, P.lambda, w4, (double)P.d[k1]) + (k1 == k2 ? P.eps : 0.0);
+      if (k1 == k2) s.im = 0.0;
+      stc(L, i, s);
+    }
+    for (int i = t; i < n * C; i += 64) {
+      const int k = i / C, c = i - k * C;
+      cd s = cd{0.0, 0.0};
+      for (int j = 0; j < m; ++j) cfma_conj(s, ldc(A, j * n + k), ldc(b, j * C + c));
+      stc(x, i, s);
+    }
+    __syncthreads();
+    // Cholesky (right-looking) in LDS; diagonal stored as L_jj
+    for (int j = 0; j < n; ++j) {
+      double piv = L[2 * (j * n + j)];
+      if (!(piv > 0.0)) piv = 1e-300;
+      const double inv = 1.0 / sqrt(piv);
+      __syncthreads();
+      for (int i = j + 1 + t; i < n; i += 64) stc(L, i * n + j, cscale(ldc(L, i * n + j), inv));
+      if (t == 0) { L[2 * (j * n + j)] = piv * inv; L[2 * (j * n + j) + 1] = 0.0; }
+      __syncthreads();
+      const int rem = n - j - 1;
+      for (int e = t; e < rem * rem; e += 64) {
+        const int i = j + 1 + e / rem, k = j + 1 + e % rem;
+        if (k > i) continue;
+        cd v = ldc(L, i * n + k);
+        cfms_aconjb(v, ldc(L, i * n + j), ldc(L, k * n + j));
+        stc(L, i * n + k, v);
+      }
+      __syncthreads();
+    }
+    // x = L^-H L^-1 c, one lane per channel
+    if (t < C) {
+      const int c = t;
+      for (int k = 0; k < n; ++k) {
+        cd s = ldc(x, k * C + c);
+        for (int p = 0; p < k; ++p) {
+          const cd l = ldc(L, k * n + p), y = ldc(x, p * C + c);
+          s = csub(s, cmul(l, y));
+        }
+        stc(x, k * C + c, cscale(s, 1.0 / L[2 * (k * n + k)]));
+      }
+      for (int k = n - 1; k >= 0; --k) {
+        cd s = ldc(x, k * C + c);
+        for (int p = k + 1; p < n; ++p) {
+          const cd l = ldc(L, p * n + k), y = ldc(x, p * C + c);
+          s = csub(s, cmulc(l, y));
+        }
+        stc(x, k * C + c, cscale(s, 1.0 / L[2 * (k * n + k)]));
+      }
+    }
+    __syncthreads();
+    // residual: FIT r = A x - b ; LOO r = b - A x
+    const double rs = P.mode == 1 ? -1.0 : 1.0;
+    for (int i = t; i < m * C; i += 64) {
+      const int j = i / C, c = i - j * C;
+      cd s = cd{0.0, 0.0};
+      for (int k = 0; k < n; ++k) cfma(s, ldc(A, j * n + k), ldc(x, k * C + c));
+      s = csub(s, ldc(b, i));
+      stc(r, i, cscale(s, rs));
+    }
+    __syncthreads();
+
+    if (P.mode == 0) {
+      // loss: ||r||^2 + x^H (lambda G + eps I) x, split over lanes
+      for (int i = t; i < m * C; i += 64) { const cd v = ldc(r, i); loss += v.re * v.re + v.im * v.im; }
+      for (int i = t; i < n * n * C; i += 64) {
+        const int c = i / (n * n), e = i - c * n * n, k1 = e / n, k2 = e - k1 * n;
+        const double g = reg_entry(P.reg, k1, k2, n, P.lambda, w4, (double)P.d[k1]) + (k1 == k2 ? P.eps : 0.0);
+        if (g != 0.0) {
+          const cd a = ldc(x, k1 * C + c), bb = ldc(x, k2 * C + c);
+          loss += g * (a.re * bb.re + a.im * bb.im);
+        }
+      }
+      for (int i = t; i < m * n; i += 64) {
+        const int j = i / n, k = i - j * n;
+        const cd a = ldc(A, i);
+        double s = 0.0;
+        for (int c = 0; c < C; ++c) {
+          // Im(conj(x) conj(A) r)
+          const cd xr = cmulc(ldc(x, k * C + c), ldc(r, j * C + c));
+          s += a.re * xr.im - a.im * xr.re;
+        }
+        T[i] = 4.0 * kPi * s;
+      }
+    } else {
+      double* Pm = sm + o.P;
+      double* w = sm + o.w;
+      double* y = sm + o.y;
+      double* v = sm + o.v;
+      double* gam = sm + o.gam;
+      double* Wm = sm + o.Wm;
+      // P = L^-1 A^H, then G = L^-H P in place, h_j = ||P_:j||^2; one lane per view
+      for (int j = t; j < m; j += 64) {
+        double h = 0.0;
+        for (int k = 0; k < n; ++k) {
+          cd s = cd{A[2 * (j * n + k)], -A[2 * (j * n + k) + 1]};
+          for (int p = 0; p < k; ++p) s = csub(s, cmul(ldc(L, k * n + p), ldc(Pm, p * m + j)));
+          s = cscale(s, 1.0 / L[2 * (k * n + k)]);
+          stc(Pm, k * m + j, s);
+          h += s.re * s.re + s.im * s.im;
+        }
+        for (int k = n - 1; k >= 0; --k) {
+          cd s = ldc(Pm, k * m + j);
+          for (int p = k + 1; p < n; ++p) s = csub(s, cmulc(ldc(L, p * n + k), ldc(Pm, p * m + j)));
+          stc(Pm, k * m + j, cscale(s, 1.0 / L[2 * (k * n + k)]));
+        }
+        const double om = 1.0 - h;
+        double rr = 0.0;
+        for (int c = 0; c < C; ++c) {
+          const cd rv = ldc(r, j * C + c);
+          rr += rv.re * rv.re + rv.im * rv.im;
+          stc(w, j * C + c, cscale(rv, 1.0 / (om * om)));
+        }
+        loss += rr / (om * om);
+        gam[j] = 2.0 * rr / (om * om * om);
+      }
+      __syncthreads();
+      // y = G w
+      for (int i = t; i < n * C; i += 64) {
+        const int k = i / C, c = i - k * C;
+        cd s = cd{0.0, 0.0};
+        for (int j = 0; j < m; ++j) cfma(s, ldc(Pm, k * m + j), ldc(w, j * C + c));
+        stc(y, i, s);
+      }
+      // Wm[p][k] = sum_i A_ip gam_i G_ki
+      for (int e = t; e < n * n; e += 64) {
+        const int p = e / n, k = e - p * n;
+        cd s = cd{0.0, 0.0};
+        for (int i = 0; i < m; ++i) cfma(s, cscale(ldc(A, i * n + p), gam[i]), ldc(Pm, k * m + i));
+        stc(Wm, e, s);
+      }
+      __syncthreads();
+      // v = w - A y
+      for (int i = t; i < m * C; i += 64) {
+        const int j = i / C, c = i - j * C;
+        cd s = ldc(w, i);
+        for (int k = 0; k < n; ++k) s = csub(s, cmul(ldc(A, j * n + k), ldc(y, k * C + c)));
+        stc(v, i, s);
+      }
+      __syncthreads();
+      for (int i = t; i < m * n; i += 64) {
+        const int j = i / n, k = i - j * n;
+        cd psi = cscale(ldc(Pm, k * m + j), gam[j]);
+        for (int c = 0; c < C; ++c) {
+          const cd vv = ldc(v, j * C + c), xx = ldc(x, k * C + c);
+          const cd rr = ldc(r, j * C + c), yy = ldc(y, k * C + c);
+          psi = csub(psi, cmulc(vv, xx));
+          psi = csub(psi, cmulc(rr, yy));
+        }
+        for (int p = 0; p < n; ++p) psi = csub(psi, cmul(ldc(Pm, p * m + j), ldc(Wm, p * n + k)));
+        const cd pa = cmul(psi, ldc(A, i));
+        T[i] = -4.0 * kPi * pa.im;
+      }
+    }
+    __syncthreads();
+    // accumulate the chain rule through theta_jk = d_k <u_j, w>
+    for (int s = 0; s < 4; ++s) {
+      const int j = t + 64 * s;
+      if (j < m) {
+        double g = 0.0;
+        for (int k = 0; k < n; ++k) g += (double)P.d[k] * T[j * n + k];
+        gu[s][0] += g * wx;
+        gu[s][1] += g * wy;
+      }
+    }
+    if (t < n) {
+      double g = 0.0;
+      for (int j = 0; j < m; ++j) g += T[j * n + t] * pj[j];
+      gd += g;
+    }
+    __syncthreads();
+  }
+
+  // block partials: [loss, grad_u (2m), grad_d (n)]
+  double* red = sm + o.red;
+  red[t] = loss;
+  __syncthreads();
+  double* out = P.partial + (size_t)blockIdx.x * P.stride;
+  if (t == 0) {
+    double s = 0.0;
+    for (int i = 0; i < 64; ++i) s += red[i];
+    out[0] = s;
+  }
+  for (int s = 0; s < 4; ++s) {
+    const int j = t + 64 * s;
+    if (j < m) { out[1 + 2 * j] = gu[s][0]; out[2 + 2 * j] = gu[s][1]; }
+  }
+  if (t < n) out[1 + 2 * m + t] = gd;
+}
+
+__global__ __launch_bounds__(256) void k_calib_reduce(CalibParams P, int nblocks) {
+  for (int i = threadIdx.x; i < P.stride; i += blockDim.x) {
+    double s = 0.0;
+    for (int bl = 0; bl < nblocks; ++bl) s += P.partial[(size_t)bl * P.stride + i];
+    if (i == 0) P.loss[0] = s;
+    else if (i <= 2 * P.m) P.grad_u[i - 1] = s;
+    else P.grad_d[i - 1 - 2 * P.m] = s;
+  }
+}
+
+int calib_blocks(int Q) { return Q < 2048 ? Q : 2048; }
+
+hipError_t launch_calib(const CalibParams& P, hipStream_t s) {
+  const int nb = calib_blocks(P.Q);
+  const size_t lds = calib_lds_bytes(P.m, P.n, P.C, P.mode);
+  hipLaunchKernelGGL(k_calib, dim3(nb), dim3(64), lds, s, P);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_calib_reduce, dim3(1), dim3(256), 0, s, P, nb);
+  return hipGetLastError();
+}
+
+// Sec. V-B update, u' = u - alpha grad_u / (eps + ||grad_u||^2) (same for d).
+__global__ __launch_bounds__(256) void k_gd_step(float2* u, float* d, const double* gu, const double* gd, int m,
+                                                 int n, double alpha, double eps_g) {
+  __shared__ double su[256], sd[256];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < 2 * m; i += 256) a += gu[i] * gu[i];
+  for (int i = threadIdx.x; i < n; i += 256) b += gd[i] * gd[i];
+  su[threadIdx.x] = a;
+  sd[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) { su[threadIdx.x] += su[threadIdx.x + w]; sd[threadIdx.x] += sd[threadIdx.x + w]; }
+    __syncthreads();
+  }
+  const double cu = alpha / (eps_g + su[0]);
+  const double cdd = alpha / (eps_g + sd[0]);
+  for (int j = threadIdx.x; j < m; j += 256) {
+    float2 v = u[j];
+    v.x = (float)((double)v.x - cu * gu[2 * j]);
+    v.y = (float)((double)v.y - cu * gu[2 * j + 1]);
+    u[j] = v;
+  }
+  for (int k = threadIdx.x; k < n; k += 256) d[k] = (float)((double)d[k] - cdd * gd[k]);
+}
+
+hipError_t launch_gd_step(float2* u, float* d, const double* gu, const double* gd, int m, int n, double alpha,
+                          double eps_g, hipStream_t s) {
+  hipLaunchKernelGGL(k_gd_step, dim3(1), dim3(256), 0, s, u, d, gu, gd, m, n, alpha, eps_g);
+  return hipGetLastError();
+}
+
+}  // namespace fdl

@@ -50,6 +50,26 @@ struct FftParams {
 };
 
 hipError_t launch_rfft2(const FftParams& P, hipStream_t s);
+
+struct CalibParams {
+  const float2* view_spec;   // [m][C][F]
+  const float2* u;           // [m]
+  const float* d;            // [n]
+  const int* freq_idx;       // [Q] or null (all F bins)
+  double* partial;           // workspace [blocks][stride]
+  double* loss;              // [1]
+  double* grad_u;            // [m][2]
+  double* grad_d;            // [n]
+  int m, n, C, H, W, Wh, F, Q;
+  double lambda, eps, bscale;
+  int reg, mode, stride;
+};
+
+size_t calib_lds_bytes(int m, int n, int C, int mode);
+int calib_blocks(int Q);
+hipError_t launch_calib(const CalibParams& P, hipStream_t s);
+hipError_t launch_gd_step(float2* u, float* d, const double* gu, const double* gd, int m, int n, double alpha,
+                          double eps_g, hipStream_t s);
 hipError_t launch_irfft2(const FftParams& P, hipStream_t s);
 
 }  // namespace fdl

@@ -151,4 +151,48 @@ int fdl_irfft2(fdl_c64* spec_dev, float* img_dev, int batch, int H, int W, void*
   return map_hip(fdl::launch_irfft2(P, reinterpret_cast<hipStream_t>(stream)));
 }
 
+size_t fdl_calib_workspace(int m, int n, int Q) {
+  if (m < 1 || n < 1 || Q < 1) return 0;
+  return (size_t)fdl::calib_blocks(Q) * (size_t)(1 + 2 * m + n) * sizeof(double);
+}
+
+int fdl_calib_grad(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_dev, int m, int n, int C, int H,
+                   int W, float lambda, float eps, int reg, int mode, const int32_t* freq_idx_dev, int Q,
+                   double* loss_dev, double* grad_u_dev, double* grad_d_dev, void* ws_dev, size_t ws_bytes,
+                   void* stream) {
+  if (!view_spec_dev || !u_dev || !d_dev || !loss_dev || !grad_u_dev || !grad_d_dev || !ws_dev) return FDL_EINVAL;
+  if (!(std::isfinite(lambda) && lambda >= 0.f) || !(std::isfinite(eps) && eps >= 0.f)) return FDL_EINVAL;
+  if (reg < FDL_REG_VIEW2 || reg > FDL_REG_L2 || (mode != FDL_LOSS_FIT && mode != FDL_LOSS_LOO)) return FDL_EINVAL;
+  if (m < 1 || m > 256 || n < 1 || n > FDL_MAX_LAYERS || C < 1 || C > FDL_MAX_CHANNELS) return FDL_ESHAPE;
+  if (H < 1 || W < 2 || (W & 1)) return FDL_ESHAPE;
+  const long long F = (long long)H * (W / 2 + 1);
+  if (F > (1LL << 30)) return FDL_ESHAPE;
+  if (!freq_idx_dev) Q = (int)F;
+  if (Q < 1) return FDL_EINVAL;
+  if (ws_bytes < fdl_calib_workspace(m, n, Q)) return FDL_ENOMEM;
+  if (fdl::calib_lds_bytes(m, n, C, mode) > 65536) return FDL_ESHAPE;
+  fdl::CalibParams P;
+  P.view_spec = reinterpret_cast<const float2*>(view_spec_dev);
+  P.u = reinterpret_cast<const float2*>(u_dev);
+  P.d = d_dev;
+  P.freq_idx = freq_idx_dev;
+  P.partial = static_cast<double*>(ws_dev);
+  P.loss = loss_dev;
+  P.grad_u = grad_u_dev;
+  P.grad_d = grad_d_dev;
+  P.m = m; P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F; P.Q = Q;
+  P.lambda = (double)lambda; P.eps = (double)eps; P.bscale = 1.0 / std::sqrt((double)H * (double)W);
+  P.reg = reg; P.mode = mode; P.stride = 1 + 2 * m + n;
+  trace("calib m n Q mode", m, n, Q, mode);
+  return map_hip(fdl::launch_calib(P, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int fdl_gd_step(fdl_f2* u_dev, float* d_dev, const double* grad_u_dev, const double* grad_d_dev, int m, int n,
+                double alpha, double eps_g, void* stream) {
+  if (!u_dev || !d_dev || !grad_u_dev || !grad_d_dev) return FDL_EINVAL;
+  if (m < 1 || n < 1 || !std::isfinite(alpha) || !(eps_g >= 0.0)) return FDL_EINVAL;
+  return map_hip(fdl::launch_gd_step(reinterpret_cast<float2*>(u_dev), d_dev, grad_u_dev, grad_d_dev, m, n, alpha,
+                                     eps_g, reinterpret_cast<hipStream_t>(stream)));
+}
+
 }  // extern "C"

@@ -1,0 +1,182 @@
+"""GPU parity for the calibration loss/gradient (paper FIT mode and the
+leave-one-out adjoint) and the normalised gradient step, against the FP64
+oracle; the LOO adjoint is also checked against central finite differences of
+the FP64 loss on every bin of the 7x7, 256^2, 16-layer workload."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import brute
+from oracle import fdl_oracle as O
+from paper_1901_06919_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def fdl():
+    import paper_1901_06919_amd as m
+    return m
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _small(seed, m, n, C, H, W):
+    rng = np.random.default_rng(seed)
+    u = rng.uniform(-2, 2, (m, 2)).astype(np.float32)
+    d = np.sort(rng.uniform(-2, 2, n)).astype(np.float32)
+    spec = O.rfft2(rng.standard_normal((m, C, H, W))).astype(np.complex64)
+    F = H * (W // 2 + 1)
+    return u, d, spec, F
+
+
+@pytest.mark.parametrize("mode", [O.LOSS_FIT, O.LOSS_LOO])
+@pytest.mark.parametrize("m,n,C,H,W,reg", [(5, 3, 1, 8, 8, O.REG_LAYER2), (9, 7, 2, 12, 16, O.REG_LAYER2),
+                                           (16, 16, 1, 8, 12, O.REG_L2), (4, 6, 3, 6, 8, O.REG_LAYER2)])
+def test_calib_small_all_bins(mode, m, n, C, H, W, reg):
+    print(f"calib mode={mode} m={m} n={n} C={C} H={H} W={W} reg={reg}", flush=True)
+    u, d, spec, F = _small(100 + m + n, m, n, C, H, W)
+    S = np.arange(F, dtype=np.int32)
+    lam, eps = 1e-2, 1e-3
+    L, gu, gd = O.calib_loss_grad(spec.astype(np.complex128), u.astype(np.float64), d.astype(np.float64), H, W,
+                                  lam, eps, reg, mode, S)
+    l2, gu2, gd2 = fdl().calib_grad(dev(spec), dev(u), dev(d), H, W, lam, eps, reg, mode, None)
+    torch.cuda.synchronize()
+    print(f"  loss {L:.6e} vs {l2.item():.6e}; rel gu {rel(gu2.cpu(), gu):.2e} gd {rel(gd2.cpu(), gd):.2e}")
+    assert abs(l2.item() - L) <= 1e-6 * abs(L)
+    assert rel(gu2.cpu().numpy(), gu) < 1e-6
+    assert rel(gd2.cpu().numpy(), gd) < 1e-6
+
+
+def _config5_inputs():
+    spec, u0, d0 = synth.config5()
+    views = O.forward_views(spec.layers.astype(np.float64), spec.u, spec.d) + spec.noise
+    b = O.rfft2(views.astype(np.float32)).astype(np.complex64)
+    return spec, u0, d0, b
+
+
+@pytest.mark.parametrize("mode,Q", [(O.LOSS_FIT, 4096), (O.LOSS_LOO, 1024)])
+def test_calib_config5_sampled_bins(mode, Q):
+    spec, u0, d0, b = _config5_inputs()
+    H, W = spec.H, spec.W
+    F = H * (W // 2 + 1)
+    S = synth.frequency_subset(F, Q, np.random.default_rng(55))
+    L, gu, gd = O.calib_loss_grad(b.astype(np.complex128), u0.astype(np.float64), d0.astype(np.float64), H, W,
+                                  spec.lam, spec.eps, spec.reg, mode, S)
+    l2, gu2, gd2 = fdl().calib_grad(dev(b), dev(u0), dev(d0), H, W, spec.lam, spec.eps, spec.reg, mode, dev(S))
+    torch.cuda.synchronize()
+    print(f"config5 mode={mode} Q={Q}: loss {L:.8e} vs {l2.item():.8e}; rel gu {rel(gu2.cpu(), gu):.2e} "
+          f"gd {rel(gd2.cpu(), gd):.2e}")
+    assert abs(l2.item() - L) <= 1e-6 * abs(L)
+    assert rel(gu2.cpu().numpy(), gu) < 1e-5
+    assert rel(gd2.cpu().numpy(), gd) < 1e-5
+
+
+def _press_loss_all_bins(b, u, d, H, W, lam, eps):
+    """LOO loss (sum over every bin) by the PRESS identity (FP64, batched numpy)."""
+    m, C = b.shape[:2]
+    wx, wy = O.flat_freqs(H, W)
+    A = O.a_matrix(u, d, wx, wy)
+    G = O.second_difference(len(d))
+    R = lam * (G.T @ G) + eps * np.eye(len(d))
+    M = np.conj(np.swapaxes(A, 1, 2)) @ A + R[None]
+    Minv = np.linalg.inv(M)
+    bb = np.transpose(b.reshape(m, C, -1), (2, 0, 1)).astype(np.complex128) / math.sqrt(H * W)
+    x = Minv @ (np.conj(np.swapaxes(A, 1, 2)) @ bb)
+    r = bb - A @ x
+    h = np.real(np.einsum("fjk,fkl,fjl->fj", A, Minv, np.conj(A)))
+    return float(np.sum(np.abs(r / (1.0 - h)[:, :, None]) ** 2))
+
+
+def test_loo_adjoint_vs_finite_differences_config5_all_bins():
+    """Hand-written LOO adjoint (all F = 33,024 bins) against FP64 central
+    differences (h = 1e-6) of the LOO loss, on a spread of coordinates."""
+    spec, u0, d0, b = _config5_inputs()
+    H, W = spec.H, spec.W
+    l2, gu2, gd2 = fdl().calib_grad(dev(b), dev(u0), dev(d0), H, W, spec.lam, spec.eps, spec.reg, O.LOSS_LOO, None)
+    torch.cuda.synchronize()
+    u = u0.astype(np.float64)
+    d = d0.astype(np.float64)
+    b64 = b.astype(np.complex128)
+    L0 = _press_loss_all_bins(b64, u, d, H, W, spec.lam, spec.eps)
+    assert abs(l2.item() - L0) <= 1e-7 * abs(L0)
+    h = 1e-6
+    checks = [("u", 0, 0), ("u", 24, 1), ("u", 48, 0), ("d", 0, None), ("d", 7, None), ("d", 15, None)]
+    for kind, i, c in checks:
+        if kind == "u":
+            up, um = u.copy(), u.copy()
+            up[i, c] += h
+            um[i, c] -= h
+            fd = (_press_loss_all_bins(b64, up, d, H, W, spec.lam, spec.eps)
+                  - _press_loss_all_bins(b64, um, d, H, W, spec.lam, spec.eps)) / (2 * h)
+            g = gu2.cpu().numpy()[i, c]
+        else:
+            dp, dm = d.copy(), d.copy()
+            dp[i] += h
+            dm[i] -= h
+            fd = (_press_loss_all_bins(b64, u, dp, H, W, spec.lam, spec.eps)
+                  - _press_loss_all_bins(b64, u, dm, H, W, spec.lam, spec.eps)) / (2 * h)
+            g = gd2.cpu().numpy()[i]
+        scale = max(np.abs(gu2.cpu().numpy()).max(), np.abs(gd2.cpu().numpy()).max())
+        print(f"  {kind}[{i},{c}] adjoint {g:+.8e} fd {fd:+.8e}")
+        assert abs(g - fd) <= 1e-5 * scale
+
+
+def test_calib_is_deterministic():
+    spec, u0, d0, b = _config5_inputs()
+    H, W = spec.H, spec.W
+    S = dev(synth.frequency_subset(H * (W // 2 + 1), 4096, np.random.default_rng(9)))
+    a = [t.clone() for t in fdl().calib_grad(dev(b), dev(u0), dev(d0), H, W, spec.lam, spec.eps, spec.reg, 1, S)]
+    c = [t.clone() for t in fdl().calib_grad(dev(b), dev(u0), dev(d0), H, W, spec.lam, spec.eps, spec.reg, 1, S)]
+    torch.cuda.synchronize()
+    for x, y in zip(a, c):
+        assert torch.equal(x, y)
+
+
+def test_gd_step_matches_oracle():
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((7, 2)).astype(np.float32)
+    d = rng.standard_normal(5).astype(np.float32)
+    gu = rng.standard_normal((7, 2))
+    gd = rng.standard_normal(5)
+    ur, dr = O.gd_step(u.astype(np.float64), d.astype(np.float64), gu, gd, 0.2, 1e-6)
+    tu, td = dev(u), dev(d)
+    fdl().gd_step(tu, td, dev(gu), dev(gd), 0.2, 1e-6)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(tu.cpu().numpy(), ur, rtol=0, atol=2e-7)
+    np.testing.assert_allclose(td.cpu().numpy(), dr, rtol=0, atol=2e-7)
+
+
+def test_calibration_trajectory_first_steps():
+    """20 LOO gradient steps (alpha 0.2, fresh 512-bin subset per step, passed
+    to both sides) on the 7x7 / 256^2 / 16-layer workload: parameters after
+    every step within 1e-4 (relative L2) of the oracle's trajectory."""
+    spec, u0, d0, b = _config5_inputs()
+    H, W = spec.H, spec.W
+    F = H * (W // 2 + 1)
+    rng = np.random.default_rng(505)
+    u_o, d_o = u0.astype(np.float64), d0.astype(np.float64)
+    tu, td = dev(u0), dev(d0)
+    tb = dev(b)
+    b64 = b.astype(np.complex128)
+    for step in range(20):
+        S = synth.frequency_subset(F, 512, rng)
+        _, gu, gd = O.calib_loss_grad(b64, u_o, d_o, H, W, spec.lam, spec.eps, spec.reg, O.LOSS_LOO, S)
+        u_o, d_o = O.gd_step(u_o, d_o, gu, gd, 0.2, 1e-6)
+        u_o, d_o = u_o.astype(np.float32).astype(np.float64), d_o.astype(np.float32).astype(np.float64)
+        _, tgu, tgd = fdl().calib_grad(tb, tu, td, H, W, spec.lam, spec.eps, spec.reg, O.LOSS_LOO, dev(S))
+        fdl().gd_step(tu, td, tgu, tgd, 0.2, 1e-6)
+        torch.cuda.synchronize()
+        eu = rel(tu.cpu().numpy(), u_o)
+        ed = rel(td.cpu().numpy(), d_o)
+        print(f"  step {step}: rel u {eu:.2e} d {ed:.2e}")
+        assert eu < 1e-4 and ed < 1e-4
