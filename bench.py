@@ -1,0 +1,256 @@
+#!/usr/bin/env python3
+"""Benchmark of the Fourier Disparity Layer hot path on one MI355X.
+
+One step = every stage of the path over one batch of synthetic input,
+inputs resident in HBM before the timed region:
+  a1  rfft2 of the 81 views x 3 channels (512^2)              -> view spectra
+  a2-a6  layer construction, 30 layers, 131,584 bins x 3 ch   -> layer spectra
+  a7  render 81 disk-aperture views at the input positions    -> view spectra
+  a8  irfft2 of the 243 rendered spectra                      -> images
+  a9  calibration loss + leave-one-out adjoint, 4096 bins of the 7x7 / 256^2 /
+      16-layer calibration workload
+  a10 normalised gradient step on (u, d)
+The workload is the 9x9-view, 512x512 RGB, 30-layer light field (jittered
+grid, 1/f^2 layers, noise 0.005, lambda 1e-3); its views are synthesised on the
+GPU by the library's own forward model (untimed set-up).
+
+value  = layer-construction frequency solves per second of the whole step
+         (131,584 bins per step; each bin's system serves the 3 channels).
+Also reported: rendered views/s, per-stage times, the roofline of the
+dominant kernel (construction, FP64 VALU-bound), and the FP64 CPU oracle
+timed on a bounded sample of the same construction.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_FP64_TFLOPS = 78.6      # MI355X vector FP64 (256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz)
+PEAK_HBM_GBS = 8000.0
+
+
+def construct_flops_per_bin(m: int, n: int, C: int) -> int:
+    """Algorithmic FP64 flops of one bin with the Toeplitz Gram (d uniform):
+    Gram 8 m (n-1), right-hand sides 8 m n C, Cholesky (4/3) n^3, two
+    triangular solves 8 n^2 C (1 complex multiply-add = 8 flops)."""
+    return 8 * m * (n - 1) + 8 * m * n * C + (4 * n ** 3) // 3 + 8 * n * n * C
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for name in ("construct_team.h", "construct_r2.hip", "fdl_device.h"):
+        with open(os.path.join(ROOT, "paper_1901_06919_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic():
+    """HBM bytes per construct launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "construct_config2_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(u, d):
+    """The FP64 oracle's construction (unchanged) on a bounded sample of bins of
+    the same 9x9 / 512^2 / 30-layer / 3-channel problem, split over worker
+    threads (numpy's LAPACK calls release the GIL; BLAS pinned to 1 thread)."""
+    import concurrent.futures
+
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import fdl_oracle as O
+
+    H = W = 512
+    u = np.asarray(u, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    m, n, C = 81, 30, 3
+    F = H * (W // 2 + 1)
+    rng = np.random.default_rng(7)
+    nbins = F                      # one full construction of the workload
+    idx = np.arange(F)
+    spec = np.zeros((m, C, H, W // 2 + 1), dtype=np.complex64)
+    flat = spec.reshape(m, C, -1)
+    flat[:, :, idx] = (rng.standard_normal((m, C, nbins)) + 1j * rng.standard_normal((m, C, nbins))).astype(np.complex64)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    chunks = np.array_split(idx, workers * 4)
+
+    def run(ch):
+        return O.construct(spec, u, d, H, W, 1e-3, 1e-3, O.REG_VIEW2, freq_index=ch)
+
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+            list(ex.map(run, chunks))
+        dt = time.perf_counter() - t0
+    return {"value": nbins / dt, "unit": "bins/s", "cores": workers, "kind": "oracle",
+            "sample": f"FP64 oracle construct of {nbins} of the {F} bins (81 views, 30 layers, 3 channels), "
+                      f"{workers} threads, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build measures one GPU only (the FDL path is run on one MI355X; "
+              "multi-GPU sharding is described, not built). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1901_06919_amd as fdl
+    from paper_1901_06919_amd import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    # ---- set-up (untimed): synthetic workload resident in HBM ----
+    c2 = synth.config2()
+    H, W = c2.H, c2.W
+    m, n, C = c2.m, c2.n, c2.C
+    F = H * (W // 2 + 1)
+    layers = torch.from_numpy(c2.layers).to(dev)
+    u = torch.from_numpy(c2.u).to(dev)
+    d_dev = torch.from_numpy(c2.d).to(dev)
+    d_host = torch.from_numpy(c2.d).clone()
+    pin = torch.zeros((m, 5), dtype=torch.float32)
+    pin[:, 0:2] = torch.from_numpy(c2.u)
+    pin_rec = fdl.view_records(pin.to(dev))
+    views_rec = fdl.view_records(torch.from_numpy(c2.views).to(dev))
+    lspec = fdl.rfft2(layers)
+    vspec = fdl.render(lspec, d_dev, pin_rec, H, W)
+    views = fdl.irfft2(vspec, H, W) + torch.from_numpy(c2.noise).to(dev)
+    del lspec, vspec, layers
+
+    c5, u5_0, d5_0 = synth.config5()
+    l5 = fdl.rfft2(torch.from_numpy(c5.layers).to(dev))
+    p5 = torch.zeros((c5.m, 5), dtype=torch.float32)
+    p5[:, 0:2] = torch.from_numpy(c5.u)
+    v5 = fdl.irfft2(fdl.render(l5, torch.from_numpy(c5.d).to(dev), fdl.view_records(p5.to(dev)), c5.H, c5.W),
+                    c5.H, c5.W) + torch.from_numpy(c5.noise).to(dev)
+    b5 = fdl.rfft2(v5)
+    del l5, v5
+    u5 = torch.from_numpy(u5_0).to(dev)
+    d5 = torch.from_numpy(d5_0).to(dev)
+    F5 = c5.H * (c5.W // 2 + 1)
+    Q5 = 4096
+    rng = np.random.default_rng(5)
+    nsub = args.warmup + args.steps
+    subsets = torch.from_numpy(np.stack([synth.frequency_subset(F5, Q5, rng) for _ in range(nsub)])).to(dev)
+    g_out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((c5.m, 2), dtype=torch.float64, device=dev),
+             torch.empty(c5.n, dtype=torch.float64, device=dev))
+    ws5 = torch.empty(fdl.calib_workspace_bytes(c5.m, c5.n, Q5), dtype=torch.uint8, device=dev)
+
+    spec = torch.empty((m, C, H, W // 2 + 1), dtype=torch.complex64, device=dev)
+    lay = torch.empty((n, C, H, W // 2 + 1), dtype=torch.complex64, device=dev)
+    rend = torch.empty((m, C, H, W // 2 + 1), dtype=torch.complex64, device=dev)
+    img = torch.empty((m, C, H, W), dtype=torch.float32, device=dev)
+    V = int(views_rec.shape[0])
+
+    stages = ["rfft2", "construct", "render", "irfft2", "calib_grad", "gd_step"]
+    ev = {s: [] for s in stages}
+
+    def step(i, record):
+        marks = []
+
+        def mark():
+            if record:
+                e = torch.cuda.Event(enable_timing=True)
+                e.record()
+                marks.append(e)
+
+        mark()
+        fdl.rfft2(views, out=spec)
+        mark()
+        fdl.construct(spec, u, d_host, H, W, c2.lam, c2.eps, c2.reg, out=lay)
+        mark()
+        fdl.render(lay, d_dev, views_rec, H, W, out=rend)
+        mark()
+        fdl.irfft2(rend, H, W, out=img)
+        mark()
+        fdl.calib_grad(b5, u5, d5, c5.H, c5.W, c5.lam, c5.eps, c5.reg, fdl.LOSS_LOO, subsets[i], out=g_out, ws=ws5)
+        mark()
+        fdl.gd_step(u5, d5, g_out[1], g_out[2], 0.2, 1e-6)
+        mark()
+        if record:
+            for s, a, b in zip(stages, marks[:-1], marks[1:]):
+                ev[s].append((a, b))
+
+    if args.copy_probe:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    for i in range(args.warmup):
+        step(i, False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    stage_us = {s: float(np.mean([a.elapsed_time(b) for a, b in ev[s]]) * 1e3) for s in stages}
+
+    flops = construct_flops_per_bin(m, n, C) * F
+    t_con = stage_us["construct"] * 1e-6
+    achieved = flops / t_con / 1e12
+    roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": load_traffic(),
+            "kernel": "k_construct<2,3,true>", "flops_per_launch": flops}
+
+    base = None
+    if not args.no_cpu_baseline:
+        base = cpu_baseline(c2.u, c2.d)
+
+    out = {
+        "metric": "layer-construction frequency solves/s",
+        "value": F / (ms_per_step * 1e-3),
+        "unit": "bins/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "9x9 views, 512x512 RGB, 30 layers linspace(-3,3), 81 disk renders; "
+                               "calibration rows on 7x7 views 256x256, 16 layers, 4096 bins",
+                   "bins": F, "views": m, "layers": n, "channels": C, "rendered_views": V},
+        "rendered_views_per_s": V / (ms_per_step * 1e-3),
+        "stage_us": stage_us,
+        "roofline": roof,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

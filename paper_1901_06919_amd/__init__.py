@@ -109,8 +109,11 @@ def _call(fn: str, *args):
 def view_records(views: torch.Tensor) -> torch.Tensor:
     """[V, 5] float rows (u, v, focus, radius, shape) -> device fdl_view records
     (the same 20 bytes per row, shape stored as int32)."""
+    if getattr(views, "_fdl_records", False):
+        return views
     v = views.to(torch.float32).contiguous().clone()
     v[:, 4] = views[:, 4].round().to(torch.int32).view(torch.float32)
+    v._fdl_records = True
     return v
 
 
