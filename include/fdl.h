@@ -184,9 +184,10 @@ int fdl_render(const fdl_c64* layer_spec_dev, const float* d_dev, int n, int C, 
  * Requires 1 <= m <= 256, 1 <= n <= FDL_MAX_LAYERS, 1 <= C <= FDL_MAX_CHANNELS,
  * Q >= 1 when freq_idx_dev != NULL, every index in [0, F) (not checked: an
  * index outside [0, F) reads outside view_spec_dev), and the per-bin system
- * must fit one block's 64 KiB of LDS: 8 * (2mn + 2n^2 + 4mC + 2nC + m + mn + 64)
- * bytes for FIT, plus 8 * (2nm + 4mC + 2nC + m + 2n^2) for LOO (FDL_ESHAPE
- * otherwise; m = 49, n = 16, C = 1 needs 44 KiB in LOO mode).
+ * must fit the LDS one block may use on the device (160 KiB on MI355X):
+ * 8 * (2mn + 2n^2 + 4mC + 2nC + m + mn + 256) bytes for FIT, plus
+ * 8 * (2nm + 4mC + 2nC + m + 2n^2) for LOO (FDL_ESHAPE otherwise; m = 49,
+ * n = 16, C = 1 needs 46 KiB in LOO mode, m = 81, n = 30, C = 3 FIT 85 KiB).
  * With FDL_REG_VIEW2 the regulariser depends on d; its derivative is not
  * included (the paper pairs calibration with the layer regulariser).
  * ------------------------------------------------------------------------- */

@@ -3,9 +3,9 @@
 // leave-one-out (LOO) view-prediction loss with its exact adjoint, and the
 // normalised gradient step of Sec. V-B.
 //
-// One wave (one block of 64 threads) handles one sampled bin at a time
-// (grid-stride over the Q bins); the small dense algebra of the bin lives in
-// LDS in FP64 and the 64 lanes split its loops.  Per bin:
+// One block of 256 threads handles one sampled bin at a time (grid-stride
+// over the Q bins); the small dense algebra of the bin lives in LDS in FP64
+// and the threads split its loops.  Per bin:
 //   A_jk = exp(2 pi i d_k p_j), M = A^H A + lambda Gamma^H Gamma + eps I = L L^H,
 //   x = M^-1 A^H b (b orthonormal: DFT / sqrt(HW)).
 // FIT:  r = A x - b, E_q = ||r||^2 + x^H (lambda G + eps I) x,
@@ -52,7 +52,7 @@ __host__ __device__ inline CalibLayout calib_layout(int m, int n, int C, int mod
   } else {
     o.P = o.w = o.y = o.v = o.gam = o.Wm = 0;
   }
-  o.red = at; at += 64;
+  o.red = at; at += 256;
   o.total = at;
   return o;
 }
@@ -77,7 +77,8 @@ __device__ __forceinline__ double reg_entry(int reg, int i, int k, int n, double
   return (i == k) ? lambda : 0.0;
 }
 
-__global__ __launch_bounds__(64) void k_calib(CalibParams P) {
+__global__ __launch_bounds__(256) void k_calib(CalibParams P) {
+  constexpr int NT = 256;
   extern __shared__ double sm[];
   const int m = P.m, n = P.n, C = P.C;
   const CalibLayout o = calib_layout(m, n, C, P.mode);
@@ -91,8 +92,8 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
   const int t = threadIdx.x;
   const size_t F = (size_t)P.F;
 
-  double gu[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};   // views j = t + 64 s
-  double gd = 0.0;                                       // layer k = t
+  double gu[2] = {0.0, 0.0};   // view j = t (m <= 256)
+  double gd = 0.0;              // layer k = t
   double loss = 0.0;
 
   for (int q = blockIdx.x; q < P.Q; q += gridDim.x) {
@@ -101,22 +102,22 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
     bin_freq(f, P.Wh, P.H, P.W, wx, wy);
     const double w2 = wx * wx + wy * wy, w4 = w2 * w2;
 
-    for (int j = t; j < m; j += 64) {
+    for (int j = t; j < m; j += NT) {
       const float2 uj = P.u[j];
       pj[j] = (double)uj.x * wx + (double)uj.y * wy;
     }
-    for (int i = t; i < m * C; i += 64) {
+    for (int i = t; i < m * C; i += NT) {
       const float2 v = P.view_spec[(size_t)i * F + f];
       stc(b, i, cd{(double)v.x * P.bscale, (double)v.y * P.bscale});
     }
     __syncthreads();
-    for (int i = t; i < m * n; i += 64) {
+    for (int i = t; i < m * n; i += NT) {
       const int j = i / n, k = i - j * n;
       stc(A, i, expi2pi((double)P.d[k] * pj[j]));
     }
     __syncthreads();
     // normal matrix (lower triangle, full storage) and right-hand sides
-    for (int i = t; i < n * n; i += 64) {
+    for (int i = t; i < n * n; i += NT) {
       const int k1 = i / n, k2 = i - k1 * n;
       if (k2 > k1) continue;
       cd s = cd{0.0, 0.0};
@@ -125,7 +126,7 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
       if (k1 == k2) s.im = 0.0;
       stc(L, i, s);
     }
-    for (int i = t; i < n * C; i += 64) {
+    for (int i = t; i < n * C; i += NT) {
       const int k = i / C, c = i - k * C;
       cd s = cd{0.0, 0.0};
       for (int j = 0; j < m; ++j) cfma_conj(s, ldc(A, j * n + k), ldc(b, j * C + c));
@@ -138,11 +139,11 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
       if (!(piv > 0.0)) piv = 1e-300;
       const double inv = 1.0 / sqrt(piv);
       __syncthreads();
-      for (int i = j + 1 + t; i < n; i += 64) stc(L, i * n + j, cscale(ldc(L, i * n + j), inv));
+      for (int i = j + 1 + t; i < n; i += NT) stc(L, i * n + j, cscale(ldc(L, i * n + j), inv));
       if (t == 0) { L[2 * (j * n + j)] = piv * inv; L[2 * (j * n + j) + 1] = 0.0; }
       __syncthreads();
       const int rem = n - j - 1;
-      for (int e = t; e < rem * rem; e += 64) {
+      for (int e = t; e < rem * rem; e += NT) {
         const int i = j + 1 + e / rem, k = j + 1 + e % rem;
         if (k > i) continue;
         cd v = ldc(L, i * n + k);
@@ -151,30 +152,30 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
       }
       __syncthreads();
     }
-    // x = L^-H L^-1 c, one lane per channel
-    if (t < C) {
-      const int c = t;
-      for (int k = 0; k < n; ++k) {
-        cd s = ldc(x, k * C + c);
-        for (int p = 0; p < k; ++p) {
-          const cd l = ldc(L, k * n + p), y = ldc(x, p * C + c);
-          s = csub(s, cmul(l, y));
-        }
-        stc(x, k * C + c, cscale(s, 1.0 / L[2 * (k * n + k)]));
+    // x = L^-H L^-1 c: column-oriented substitutions, threads over (row, channel)
+    for (int k = 0; k < n; ++k) {
+      const double inv = 1.0 / L[2 * (k * n + k)];
+      if (t < C) stc(x, k * C + t, cscale(ldc(x, k * C + t), inv));
+      __syncthreads();
+      for (int e = t; e < (n - k - 1) * C; e += NT) {
+        const int i = k + 1 + e / C, c = e % C;
+        stc(x, i * C + c, csub(ldc(x, i * C + c), cmul(ldc(L, i * n + k), ldc(x, k * C + c))));
       }
-      for (int k = n - 1; k >= 0; --k) {
-        cd s = ldc(x, k * C + c);
-        for (int p = k + 1; p < n; ++p) {
-          const cd l = ldc(L, p * n + k), y = ldc(x, p * C + c);
-          s = csub(s, cmulc(l, y));
-        }
-        stc(x, k * C + c, cscale(s, 1.0 / L[2 * (k * n + k)]));
-      }
+      __syncthreads();
     }
-    __syncthreads();
+    for (int k = n - 1; k >= 0; --k) {
+      const double inv = 1.0 / L[2 * (k * n + k)];
+      if (t < C) stc(x, k * C + t, cscale(ldc(x, k * C + t), inv));
+      __syncthreads();
+      for (int e = t; e < k * C; e += NT) {
+        const int i = e / C, c = e % C;
+        stc(x, i * C + c, csub(ldc(x, i * C + c), cmulc(ldc(L, k * n + i), ldc(x, k * C + c))));
+      }
+      __syncthreads();
+    }
     // residual: FIT r = A x - b ; LOO r = b - A x
     const double rs = P.mode == 1 ? -1.0 : 1.0;
-    for (int i = t; i < m * C; i += 64) {
+    for (int i = t; i < m * C; i += NT) {
       const int j = i / C, c = i - j * C;
       cd s = cd{0.0, 0.0};
       for (int k = 0; k < n; ++k) cfma(s, ldc(A, j * n + k), ldc(x, k * C + c));
@@ -185,8 +186,8 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
 
     if (P.mode == 0) {
       // loss: ||r||^2 + x^H (lambda G + eps I) x, split over lanes
-      for (int i = t; i < m * C; i += 64) { const cd v = ldc(r, i); loss += v.re * v.re + v.im * v.im; }
-      for (int i = t; i < n * n * C; i += 64) {
+      for (int i = t; i < m * C; i += NT) { const cd v = ldc(r, i); loss += v.re * v.re + v.im * v.im; }
+      for (int i = t; i < n * n * C; i += NT) {
         const int c = i / (n * n), e = i - c * n * n, k1 = e / n, k2 = e - k1 * n;
         const double g = reg_entry(P.reg, k1, k2, n, P.lambda, w4, (double)P.d[k1]) + (k1 == k2 ? P.eps : 0.0);
         if (g != 0.0) {
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
           loss += g * (a.re * bb.re + a.im * bb.im);
         }
       }
-      for (int i = t; i < m * n; i += 64) {
+      for (int i = t; i < m * n; i += NT) {
         const int j = i / n, k = i - j * n;
         const cd a = ldc(A, i);
         double s = 0.0;
@@ -212,20 +213,28 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
       double* v = sm + o.v;
       double* gam = sm + o.gam;
       double* Wm = sm + o.Wm;
-      // P = L^-1 A^H, then G = L^-H P in place, h_j = ||P_:j||^2; one lane per view
-      for (int j = t; j < m; j += 64) {
+      // P = L^-1 A^H, then G = L^-H P in place: column-oriented substitutions,
+      // threads over (row, view); h_j = ||P_:j||^2 between the two sweeps
+      for (int e = t; e < n * m; e += NT) {
+        const int k = e / m, j = e - k * m;
+        stc(Pm, e, cd{A[2 * (j * n + k)], -A[2 * (j * n + k) + 1]});
+      }
+      __syncthreads();
+      for (int k = 0; k < n; ++k) {
+        const double inv = 1.0 / L[2 * (k * n + k)];
+        for (int j = t; j < m; j += NT) stc(Pm, k * m + j, cscale(ldc(Pm, k * m + j), inv));
+        __syncthreads();
+        for (int e = t; e < (n - k - 1) * m; e += NT) {
+          const int i = k + 1 + e / m, j = e % m;
+          stc(Pm, i * m + j, csub(ldc(Pm, i * m + j), cmul(ldc(L, i * n + k), ldc(Pm, k * m + j))));
+        }
+        __syncthreads();
+      }
+      for (int j = t; j < m; j += NT) {
         double h = 0.0;
         for (int k = 0; k < n; ++k) {
-          cd s = cd{A[2 * (j * n + k)], -A[2 * (j * n + k) + 1]};
-          for (int p = 0; p < k; ++p) s = csub(s, cmul(ldc(L, k * n + p), ldc(Pm, p * m + j)));
-          s = cscale(s, 1.0 / L[2 * (k * n + k)]);
-          stc(Pm, k * m + j, s);
-          h += s.re * s.re + s.im * s.im;
-        }
-        for (int k = n - 1; k >= 0; --k) {
-          cd s = ldc(Pm, k * m + j);
-          for (int p = k + 1; p < n; ++p) s = csub(s, cmulc(ldc(L, p * n + k), ldc(Pm, p * m + j)));
-          stc(Pm, k * m + j, cscale(s, 1.0 / L[2 * (k * n + k)]));
+          const cd v = ldc(Pm, k * m + j);
+          h += v.re * v.re + v.im * v.im;
         }
         const double om = 1.0 - h;
         double rr = 0.0;
@@ -238,15 +247,25 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
         gam[j] = 2.0 * rr / (om * om * om);
       }
       __syncthreads();
+      for (int k = n - 1; k >= 0; --k) {
+        const double inv = 1.0 / L[2 * (k * n + k)];
+        for (int j = t; j < m; j += NT) stc(Pm, k * m + j, cscale(ldc(Pm, k * m + j), inv));
+        __syncthreads();
+        for (int e = t; e < k * m; e += NT) {
+          const int i = e / m, j = e % m;
+          stc(Pm, i * m + j, csub(ldc(Pm, i * m + j), cmulc(ldc(L, k * n + i), ldc(Pm, k * m + j))));
+        }
+        __syncthreads();
+      }
       // y = G w
-      for (int i = t; i < n * C; i += 64) {
+      for (int i = t; i < n * C; i += NT) {
         const int k = i / C, c = i - k * C;
         cd s = cd{0.0, 0.0};
         for (int j = 0; j < m; ++j) cfma(s, ldc(Pm, k * m + j), ldc(w, j * C + c));
         stc(y, i, s);
       }
       // Wm[p][k] = sum_i A_ip gam_i G_ki
-      for (int e = t; e < n * n; e += 64) {
+      for (int e = t; e < n * n; e += NT) {
         const int p = e / n, k = e - p * n;
         cd s = cd{0.0, 0.0};
         for (int i = 0; i < m; ++i) cfma(s, cscale(ldc(A, i * n + p), gam[i]), ldc(Pm, k * m + i));
@@ -254,14 +273,14 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
       }
       __syncthreads();
       // v = w - A y
-      for (int i = t; i < m * C; i += 64) {
+      for (int i = t; i < m * C; i += NT) {
         const int j = i / C, c = i - j * C;
         cd s = ldc(w, i);
         for (int k = 0; k < n; ++k) s = csub(s, cmul(ldc(A, j * n + k), ldc(y, k * C + c)));
         stc(v, i, s);
       }
       __syncthreads();
-      for (int i = t; i < m * n; i += 64) {
+      for (int i = t; i < m * n; i += NT) {
         const int j = i / n, k = i - j * n;
         cd psi = cscale(ldc(Pm, k * m + j), gam[j]);
         for (int c = 0; c < C; ++c) {
@@ -277,14 +296,11 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
     }
     __syncthreads();
     // accumulate the chain rule through theta_jk = d_k <u_j, w>
-    for (int s = 0; s < 4; ++s) {
-      const int j = t + 64 * s;
-      if (j < m) {
-        double g = 0.0;
-        for (int k = 0; k < n; ++k) g += (double)P.d[k] * T[j * n + k];
-        gu[s][0] += g * wx;
-        gu[s][1] += g * wy;
-      }
+    if (t < m) {
+      double g = 0.0;
+      for (int k = 0; k < n; ++k) g += (double)P.d[k] * T[t * n + k];
+      gu[0] += g * wx;
+      gu[1] += g * wy;
     }
     if (t < n) {
       double g = 0.0;
@@ -301,35 +317,57 @@ __global__ __launch_bounds__(64) void k_calib(CalibParams P) {
   double* out = P.partial + (size_t)blockIdx.x * P.stride;
   if (t == 0) {
     double s = 0.0;
-    for (int i = 0; i < 64; ++i) s += red[i];
+    for (int i = 0; i < NT; ++i) s += red[i];
     out[0] = s;
   }
-  for (int s = 0; s < 4; ++s) {
-    const int j = t + 64 * s;
-    if (j < m) { out[1 + 2 * j] = gu[s][0]; out[2 + 2 * j] = gu[s][1]; }
-  }
+  if (t < m) { out[1 + 2 * t] = gu[0]; out[2 + 2 * t] = gu[1]; }
   if (t < n) out[1 + 2 * m + t] = gd;
 }
 
+// One block per output value: each thread sums a strided subset of the block
+// partials, then a fixed-shape tree in LDS; the order never depends on timing.
 __global__ __launch_bounds__(256) void k_calib_reduce(CalibParams P, int nblocks) {
-  for (int i = threadIdx.x; i < P.stride; i += blockDim.x) {
-    double s = 0.0;
-    for (int bl = 0; bl < nblocks; ++bl) s += P.partial[(size_t)bl * P.stride + i];
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int bl = threadIdx.x; bl < nblocks; bl += 256) s += P.partial[(size_t)bl * P.stride + i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    s = red[0];
     if (i == 0) P.loss[0] = s;
     else if (i <= 2 * P.m) P.grad_u[i - 1] = s;
     else P.grad_d[i - 1 - 2 * P.m] = s;
   }
 }
 
-int calib_blocks(int Q) { return Q < 2048 ? Q : 2048; }
+// Blocks resident at once: 256 CUs x (blocks whose LDS fits one CU), at most
+// the workspace bound.
+int calib_blocks(int Q, size_t lds_per_block) {
+  size_t per_cu = lds_per_block ? (size_t)163840 / lds_per_block : 8;
+  if (per_cu < 1) per_cu = 1;
+  if (per_cu > 8) per_cu = 8;
+  size_t nb = 256 * per_cu;
+  if (nb > (size_t)kCalibMaxBlocks) nb = kCalibMaxBlocks;
+  return Q < (int)nb ? Q : (int)nb;
+}
 
 hipError_t launch_calib(const CalibParams& P, hipStream_t s) {
-  const int nb = calib_blocks(P.Q);
   const size_t lds = calib_lds_bytes(P.m, P.n, P.C, P.mode);
-  hipLaunchKernelGGL(k_calib, dim3(nb), dim3(64), lds, s, P);
+  const int nb = calib_blocks(P.Q, lds);
+  static size_t opted = 65536;
+  if (lds > opted) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_calib), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    opted = lds;
+  }
+  hipLaunchKernelGGL(k_calib, dim3(nb), dim3(256), lds, s, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_calib_reduce, dim3(1), dim3(256), 0, s, P, nb);
+  hipLaunchKernelGGL(k_calib_reduce, dim3(P.stride), dim3(256), 0, s, P, nb);
   return hipGetLastError();
 }
 

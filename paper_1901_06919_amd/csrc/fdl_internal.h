@@ -49,6 +49,7 @@ struct FftParams {
   int col_tc;       // columns per block in the column pass
 };
 
+size_t fft_lds_limit();
 hipError_t launch_rfft2(const FftParams& P, hipStream_t s);
 
 struct CalibParams {
@@ -66,7 +67,8 @@ struct CalibParams {
 };
 
 size_t calib_lds_bytes(int m, int n, int C, int mode);
-int calib_blocks(int Q);
+constexpr int kCalibMaxBlocks = 2048;
+int calib_blocks(int Q, size_t lds_per_block);
 hipError_t launch_calib(const CalibParams& P, hipStream_t s);
 hipError_t launch_gd_step(float2* u, float* d, const double* gu, const double* gd, int m, int n, double alpha,
                           double eps_g, hipStream_t s);

@@ -42,27 +42,30 @@ __device__ __forceinline__ float2 twiddle(float r) {
 }
 
 // One Stockham stage of radix R over a length-N sequence held in LDS.
-template <bool INV>
+template <int R, bool INV>
 __device__ __forceinline__ void stockham_stage(const float2* __restrict__ in, float2* __restrict__ out, int N, int Ns,
-                                               int R, int t, int G) {
+                                               int t, int G) {
   const int nb = N / R;
   const float sgn = INV ? 1.0f : -1.0f;
+  const float inv_span = 1.0f / (float)(Ns * R);
   for (int j = t; j < nb; j += G) {
     const int k = j % Ns;
-    float2 v[4];
+    float2 v[R];
+#pragma unroll
     for (int r = 0; r < R; ++r) v[r] = in[j + r * nb];
     if (Ns > 1) {
-      const float a = sgn * (float)k / (float)(Ns * R);
+      const float a = sgn * (float)k * inv_span;
+#pragma unroll
       for (int r = 1; r < R; ++r) v[r] = f2mul(v[r], twiddle(a * (float)r));
     }
-    if (R == 4) {
+    if constexpr (R == 4) {
       const float2 a0 = f2add(v[0], v[2]), a1 = f2sub(v[0], v[2]);
       const float2 a2 = f2add(v[1], v[3]), a3 = rot90<INV>(f2sub(v[1], v[3]));
       v[0] = f2add(a0, a2);
       v[2] = f2sub(a0, a2);
       v[1] = f2add(a1, a3);
       v[3] = f2sub(a1, a3);
-    } else if (R == 2) {
+    } else if constexpr (R == 2) {
       const float2 a0 = v[0];
       v[0] = f2add(a0, v[1]);
       v[1] = f2sub(a0, v[1]);
@@ -75,6 +78,7 @@ __device__ __forceinline__ void stockham_stage(const float2* __restrict__ in, fl
       v[2] = f2sub(t2, s);
     }
     const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
     for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
   }
 }
@@ -88,7 +92,9 @@ __device__ __forceinline__ float2* lds_fft(float2* b0, float2* b1, const FftPlan
   float2* out = b1;
   for (int s = 0; s < plan.nst; ++s) {
     const int R = plan.radix[s];
-    stockham_stage<INV>(in, out, plan.N, Ns, R, t, G);
+    if (R == 4) stockham_stage<4, INV>(in, out, plan.N, Ns, t, G);
+    else if (R == 2) stockham_stage<2, INV>(in, out, plan.N, Ns, t, G);
+    else stockham_stage<3, INV>(in, out, plan.N, Ns, t, G);
     __syncthreads();
     Ns *= R;
     float2* tmp = in;
@@ -172,18 +178,46 @@ __global__ __launch_bounds__(256) void k_fft_cols(float2* __restrict__ data, int
   const int lc = threadIdx.x / G;
   const int t = threadIdx.x - lc * G;
   float2* base = data + (size_t)img * H * Wh;
+  const int CS = 2 * H + 1;   // odd column stride: the transposed accesses spread over the LDS banks
   // transpose-load: lds[c][y]
   for (int q = threadIdx.x; q < H * TC; q += blockDim.x) {
     const int y = q / TC, c = q - y * TC;
-    if (c0 + c < Wh) lds[(size_t)c * 2 * H + y] = base[(size_t)y * Wh + c0 + c];
+    if (c0 + c < Wh) lds[(size_t)c * CS + y] = base[(size_t)y * Wh + c0 + c];
   }
   __syncthreads();
-  float2* b0 = lds + (size_t)lc * 2 * H;
+  float2* b0 = lds + (size_t)lc * CS;
   const float2* r = lds_fft<INV>(b0, b0 + H, plan, t, G);
   const size_t roff = (size_t)(r - b0);   // 0 or H: same for every column
   for (int q = threadIdx.x; q < H * TC; q += blockDim.x) {
     const int y = q / TC, c = q - y * TC;
-    if (c0 + c < Wh) base[(size_t)y * Wh + c0 + c] = lds[(size_t)c * 2 * H + roff + y];
+    if (c0 + c < Wh) base[(size_t)y * Wh + c0 + c] = lds[(size_t)c * CS + roff + y];
+  }
+}
+
+// Largest dynamic LDS a block may request on this device (opted in once per
+// kernel when above the 64 KiB default).
+static size_t max_block_lds() {
+  static size_t cached = 0;
+  if (!cached) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      cached = (size_t)v;
+    else
+      cached = 65536;
+  }
+  return cached;
+}
+
+size_t fft_lds_limit() { return max_block_lds(); }
+
+template <bool INV>
+static void opt_in_lds(size_t bytes) {
+  static size_t done = 65536;
+  if (bytes > done) {
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_cols<INV>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)bytes);
+    done = bytes;
   }
 }
 
@@ -212,7 +246,8 @@ hipError_t launch_rfft2(const FftParams& P, hipStream_t s) {
     const int TC = P.col_tc;
     const int G = 256 / TC;
     const int tiles = (Wh + TC - 1) / TC;
-    const size_t lds = (size_t)TC * 2 * H * sizeof(float2);
+    const size_t lds = (size_t)TC * (2 * H + 1) * sizeof(float2);
+    opt_in_lds<false>(lds);
     hipLaunchKernelGGL(k_fft_cols<false>, dim3(P.batch * tiles), dim3(TC * G), lds, s, P.cplx, P.batch, H, Wh,
                        tiles, P.col_plan, G, TC);
   }
@@ -226,7 +261,8 @@ hipError_t launch_irfft2(const FftParams& P, hipStream_t s) {
     const int TC = P.col_tc;
     const int G = 256 / TC;
     const int tiles = (Wh + TC - 1) / TC;
-    const size_t lds = (size_t)TC * 2 * H * sizeof(float2);
+    const size_t lds = (size_t)TC * (2 * H + 1) * sizeof(float2);
+    opt_in_lds<true>(lds);
     hipLaunchKernelGGL(k_fft_cols<true>, dim3(P.batch * tiles), dim3(TC * G), lds, s, P.cplx, P.batch, H, Wh,
                        tiles, P.col_plan, G, TC);
     hipError_t e = hipGetLastError();

@@ -62,8 +62,10 @@ int fft_params(int batch, int H, int W, fdl::FftParams& P) {
   P.batch = batch;
   P.H = H;
   P.W = W;
+  // columns per block: up to 16 (128-byte row segments), within the LDS limit
+  const size_t limit = fdl::fft_lds_limit() < 131072 ? fdl::fft_lds_limit() : 131072;
   int tc = 16;
-  while (tc > 1 && (size_t)tc * 2 * H * 8 > 65536) tc /= 2;
+  while (tc > 1 && (size_t)tc * (2 * H + 1) * 8 > limit) tc /= 2;
   P.col_tc = tc;
   return FDL_OK;
 }
@@ -153,7 +155,7 @@ int fdl_irfft2(fdl_c64* spec_dev, float* img_dev, int batch, int H, int W, void*
 
 size_t fdl_calib_workspace(int m, int n, int Q) {
   if (m < 1 || n < 1 || Q < 1) return 0;
-  return (size_t)fdl::calib_blocks(Q) * (size_t)(1 + 2 * m + n) * sizeof(double);
+  return (size_t)(Q < fdl::kCalibMaxBlocks ? Q : fdl::kCalibMaxBlocks) * (size_t)(1 + 2 * m + n) * sizeof(double);
 }
 
 int fdl_calib_grad(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_dev, int m, int n, int C, int H,
@@ -170,7 +172,7 @@ int fdl_calib_grad(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const floa
   if (!freq_idx_dev) Q = (int)F;
   if (Q < 1) return FDL_EINVAL;
   if (ws_bytes < fdl_calib_workspace(m, n, Q)) return FDL_ENOMEM;
-  if (fdl::calib_lds_bytes(m, n, C, mode) > 65536) return FDL_ESHAPE;
+  if (fdl::calib_lds_bytes(m, n, C, mode) > fdl::fft_lds_limit()) return FDL_ESHAPE;
   fdl::CalibParams P;
   P.view_spec = reinterpret_cast<const float2*>(view_spec_dev);
   P.u = reinterpret_cast<const float2*>(u_dev);
