@@ -105,12 +105,89 @@ def cpu_baseline(u, d):
                       f"{workers} threads, {dt:.1f} s"}
 
 
+def systems(fdl, synth, dev, serve_seconds: float):
+    """Batching: 64 uneven light fields (grids 3..9, 128^2..512^2 incl. 384,
+    8..32 layers, 1 channel) -- plain per-light-field calls vs the autotuned
+    batched plan vs the plan replayed from a HIP graph.  Serving: open-loop
+    Poisson stream at 200 req/s (20% construct, 80% render) against 8 resident
+    9x9 / 512^2 RGB / 30-layer light fields, HBM-footprint admission."""
+    import numpy as np
+    import torch
+
+    out = {}
+    g = torch.Generator(device=dev).manual_seed(3)
+    items = []
+    for i in range(64):
+        gsz, side, n = synth.config3_shape(i)
+        u = torch.from_numpy(synth.centered_grid_positions(gsz)).to(dev)
+        m = u.shape[0]
+        spec = torch.randn((m, 1, side, side // 2 + 1), dtype=torch.complex64, device=dev, generator=g)
+        d = torch.linspace(-2.0, 2.0, n)
+        items.append(dict(view_spec=spec, u=u, d=d.to(dev), d_host=d, H=side, W=side, lam=1e-2, eps=1e-3, reg=0,
+                          out=torch.empty((n, 1, side, side // 2 + 1), dtype=torch.complex64, device=dev)))
+    bins = sum(it["H"] * (it["W"] // 2 + 1) for it in items)
+
+    def plain():
+        for it in items:
+            fdl.construct(it["view_spec"], it["u"], it["d_host"], it["H"], it["W"], it["lam"], it["eps"], it["reg"],
+                          out=it["out"])
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / reps
+
+    t_plain = timed(plain)
+    plan = fdl.BatchPlan(items, mode=1)
+    plan.autotune(reps=2)
+    t_batch = timed(plan.execute)
+    gr = torch.cuda.CUDAGraph()
+    st = torch.cuda.Stream(device=dev)
+    st.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(st):
+        with torch.cuda.graph(gr, stream=st):
+            plan.execute()
+    torch.cuda.current_stream(dev).wait_stream(st)
+    t_graph = timed(gr.replay)
+    out["batching"] = {"light_fields": 64, "bins": bins, "plain_ms": t_plain, "batched_ms": t_batch,
+                       "graph_ms": t_graph, "speedup_vs_plain": t_plain / min(t_batch, t_graph),
+                       "tuning": plan.tuning(), "launches": plan.launches}
+    plan.close()
+    del items
+    torch.cuda.empty_cache()
+
+    if serve_seconds > 0:
+        from paper_1901_06919_amd.serve import FDLServer, PoolEntry
+        c2 = synth.config2(H=8, W=8)          # positions / disparities only
+        pool = []
+        d = torch.from_numpy(c2.d)
+        for i in range(8):
+            spec = torch.randn((81, 3, 512, 257), dtype=torch.complex64, device=dev, generator=g)
+            pool.append(PoolEntry(spec, torch.from_numpy(c2.u).to(dev), d, d.to(dev), 512, 512, 1e-3, 1e-3, 0))
+        srv = FDLServer(pool, hbm_budget=2 << 30, max_render_batch=16, max_inflight=8)
+        reqs = synth.config4_requests(rate=200.0, duration=serve_seconds, pool=8, seed=4)
+        for i, r in enumerate(reqs):
+            r.rid = i
+        srv.run(reqs[: max(1, len(reqs) // 10)])          # warm-up slice
+        st = srv.run(reqs)
+        out["serving"] = st.summary()
+        del srv, pool
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-systems", action="store_true")
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
@@ -224,6 +301,12 @@ def main():
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": load_traffic(),
             "kernel": "k_construct<2,3,true>", "flops_per_launch": flops}
 
+    sysres = None
+    if not args.no_systems:
+        del spec, lay, rend, img, views, b5
+        torch.cuda.empty_cache()
+        sysres = systems(fdl, synth, dev, args.serve_seconds)
+
     base = None
     if not args.no_cpu_baseline:
         base = cpu_baseline(c2.u, c2.d)
@@ -249,6 +332,13 @@ def main():
         "roofline": roof,
         "cpu_baseline": base,
     }
+    if sysres is not None:
+        out["batching"] = sysres.get("batching")
+        sv = sysres.get("serving")
+        if sv:
+            out["serving"] = sv
+            out["p50_request_ms"] = sv.get("all_p50_ms")
+            out["p99_request_ms"] = sv.get("all_p99_ms")
     print(json.dumps(out))
 
 

@@ -210,7 +210,7 @@ int fdl_gd_step(fdl_f2* u_dev, float* d_dev, const double* grad_u_dev, const dou
  * fdl_construct for each light field) in ONE persistent kernel launch.
  *
  * fdl_batch_plan_create reads a HOST array of B descriptors, validates them,
- * chooses the launch shape (from the autotune table when one is loaded), and
+ * chooses the launch shape (defaults, or the autotuner's choice), and
  * uploads the descriptors and a work table to device memory it allocates.
  * The plan keeps the device pointers of the descriptors until it is destroyed:
  * the buffers they point at must stay valid while the plan is executed.
@@ -228,9 +228,34 @@ typedef struct fdl_lf_desc {
 
 typedef struct fdl_batch_plan fdl_batch_plan;
 
-int fdl_batch_plan_create(const fdl_lf_desc* descs_host, int B, int tile_bins, fdl_batch_plan** plan_out);
+/* descs_host: B descriptors in HOST memory (their pointers are device
+ * pointers).  Light fields are grouped by channel count, disparity class and
+ * row-slot class (n <= 16 or n <= 32).  mode 0 = flat: one block per 16-bin
+ * tile, one launch per group; mode 1 = persistent: a grid of (blocks per CU x
+ * CUs) blocks pulls tiles from an atomic queue, one launch per group; mode 2
+ * = flat single: every light field through the n <= 32 solver, so one launch
+ * covers all light fields of a channel/disparity class.
+ * Tiles are ordered largest light field first.  The disparities of each light
+ * field are read once (blocking) and classified as fdl_construct does.
+ * Argument errors as fdl_construct. */
+int fdl_batch_plan_create(const fdl_lf_desc* descs_host, int B, int mode, fdl_batch_plan** plan_out);
+/* Enqueue the plan's launch(es) on `stream`; allocates nothing and issues no
+ * memset (each persistent launch's last block resets its queue), so it may be
+ * captured in a HIP graph and replayed.  Executions of one plan must not
+ * overlap in time (they share the queue counters). */
 int fdl_batch_plan_execute(const fdl_batch_plan* plan, void* stream);
-int fdl_batch_plan_info(const fdl_batch_plan* plan, int64_t* total_bins, int32_t* grid, int32_t* tile_bins);
+/* Totals of the current setting: bins over all light fields, blocks over all
+ * launches, launches per execution. */
+int fdl_batch_plan_info(const fdl_batch_plan* plan, int64_t* total_bins, int32_t* grid, int32_t* launches);
+int fdl_batch_plan_launches(const fdl_batch_plan* plan);
+/* Autotuner: times the candidates {flat}, {flat single} and {persistent, chunk 1 or 4 tiles
+ * per queue access, 1/2/4 blocks per CU} on the plan's own data (`reps` timed
+ * executions each after a warm-up, synchronising `stream`), keeps the fastest
+ * and returns its time in best_ms.  Overwrites the plan's outputs; not
+ * capturable. */
+int fdl_batch_plan_autotune(fdl_batch_plan* plan, int reps, void* stream, float* best_ms);
+int fdl_batch_plan_get_tuning(const fdl_batch_plan* plan, int32_t* mode, int32_t* chunk, int32_t* grid_per_cu);
+int fdl_batch_plan_set_tuning(fdl_batch_plan* plan, int32_t mode, int32_t chunk, int32_t grid_per_cu);
 int fdl_batch_plan_destroy(fdl_batch_plan* plan);
 
 #ifdef __cplusplus

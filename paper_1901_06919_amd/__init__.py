@@ -79,6 +79,14 @@ def lib():
                                           ctypes.POINTER(i32)]
         L.fdl_batch_plan_destroy.restype = i32
         L.fdl_batch_plan_destroy.argtypes = [vp]
+        L.fdl_batch_plan_launches.restype = i32
+        L.fdl_batch_plan_launches.argtypes = [vp]
+        L.fdl_batch_plan_autotune.restype = i32
+        L.fdl_batch_plan_autotune.argtypes = [vp, i32, vp, ctypes.POINTER(f32)]
+        L.fdl_batch_plan_get_tuning.restype = i32
+        L.fdl_batch_plan_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.fdl_batch_plan_set_tuning.restype = i32
+        L.fdl_batch_plan_set_tuning.argtypes = [vp, i32, i32, i32]
     _lib = L
     return L
 
@@ -228,3 +236,78 @@ def gd_step(u: torch.Tensor, d: torch.Tensor, grad_u: torch.Tensor, grad_d: torc
     _check(grad_d, torch.float64, (n,), "grad_d")
     _call("fdl_gd_step", u.data_ptr(), d.data_ptr(), grad_u.data_ptr(), grad_d.data_ptr(), m, n,
           float(alpha), float(eps_g), _stream(u))
+
+
+class LFDesc(ctypes.Structure):
+    """Mirror of fdl_lf_desc."""
+    _fields_ = [("view_spec", ctypes.c_void_p), ("u", ctypes.c_void_p), ("d", ctypes.c_void_p),
+                ("layer_spec", ctypes.c_void_p), ("status", ctypes.c_void_p),
+                ("m", ctypes.c_int32), ("n", ctypes.c_int32), ("C", ctypes.c_int32), ("H", ctypes.c_int32),
+                ("W", ctypes.c_int32), ("reg", ctypes.c_int32), ("lam", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+class BatchPlan:
+    """Persistent batched construction over many light fields (fdl_batch_plan_*).
+
+    ``items`` is a list of dicts with keys view_spec [m,C,H,W//2+1] c64, u [m,2]
+    f32, d [n] f32 (device), out [n,C,H,W//2+1] c64, H, W, lam, eps, reg and
+    optionally status [1] i32.  The tensors must stay alive while the plan is
+    used (the plan stores their device pointers)."""
+
+    def __init__(self, items, mode: int = 0):
+        self._items = items
+        arr = (LFDesc * len(items))()
+        for i, it in enumerate(items):
+            vs, u, d, out = it["view_spec"], it["u"], it["d"], it["out"]
+            m, C = vs.shape[:2]
+            n = d.shape[0]
+            H, W = it["H"], it["W"]
+            _check(vs, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
+            _check(u, torch.float32, (m, 2), "u")
+            _check(d, torch.float32, (n,), "d")
+            _check(out, torch.complex64, (n, C, H, W // 2 + 1), "out")
+            st = it.get("status")
+            arr[i] = LFDesc(vs.data_ptr(), u.data_ptr(), d.data_ptr(), out.data_ptr(),
+                            st.data_ptr() if st is not None else 0, m, n, C, H, W, int(it.get("reg", REG_VIEW2)),
+                            float(it["lam"]), float(it["eps"]))
+        self._descs = arr
+        h = ctypes.c_void_p()
+        _call("fdl_batch_plan_create", ctypes.cast(arr, ctypes.c_void_p), len(items), int(mode), ctypes.byref(h))
+        self._h = h
+
+    def execute(self, stream=None):
+        s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+        _call("fdl_batch_plan_execute", self._h, s)
+
+    def autotune(self, reps: int = 3) -> float:
+        ms = ctypes.c_float()
+        _call("fdl_batch_plan_autotune", self._h, int(reps), torch.cuda.current_stream().cuda_stream, ctypes.byref(ms))
+        return float(ms.value)
+
+    @property
+    def launches(self) -> int:
+        return int(lib().fdl_batch_plan_launches(self._h))
+
+    def tuning(self):
+        a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _call("fdl_batch_plan_get_tuning", self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
+        return {"mode": a.value, "chunk": b.value, "grid_per_cu": c.value}
+
+    def set_tuning(self, mode: int, chunk: int = 1, grid_per_cu: int = 2):
+        _call("fdl_batch_plan_set_tuning", self._h, int(mode), int(chunk), int(grid_per_cu))
+
+    def info(self):
+        tb, g, t = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        _call("fdl_batch_plan_info", self._h, ctypes.byref(tb), ctypes.byref(g), ctypes.byref(t))
+        return {"total_bins": tb.value, "grid": g.value, "launches": t.value}
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().fdl_batch_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

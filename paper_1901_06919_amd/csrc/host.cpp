@@ -32,19 +32,6 @@ void trace(const char* what, int a, int b, int c, int d) {
   if (std::getenv("FDL_TRACE")) std::fprintf(stderr, "fdl: %s %d %d %d %d\n", what, a, b, c, d);
 }
 
-// Classify the disparities: an arithmetic progression up to float rounding
-// lets the kernels build A^H A from n Toeplitz moment sums.
-void classify_disparities(const float* d, int n, fdl::ConstructParams& P) {
-  double dmax = 0.0, eta = 0.0;
-  for (int k = 0; k < 32; ++k) P.d[k] = k < n ? (double)d[k] : 0.0;
-  for (int k = 0; k < n; ++k) dmax = std::fmax(dmax, std::fabs(P.d[k]));
-  for (int k1 = 0; k1 < n; ++k1)
-    for (int k2 = k1 + 1; k2 < n; ++k2)
-      eta = std::fmax(eta, std::fabs((P.d[k2] - P.d[k1]) - (P.d[k2 - k1] - P.d[0])));
-  P.eta_max = eta;
-  P.toeplitz = eta <= 1e-5 * (1.0 + dmax) ? 1 : 0;
-}
-
 // Factor N = 4^a 2^b 3^c into Stockham radices; false if N has another factor.
 bool make_plan(int N, fdl::FftPlan& plan) {
   plan.N = N;
@@ -71,6 +58,22 @@ int fft_params(int batch, int H, int W, fdl::FftParams& P) {
 }
 
 }  // namespace
+
+namespace fdl_host {
+// Classify the disparities: an arithmetic progression up to float rounding
+// lets the kernels build A^H A from n Toeplitz moment sums.
+void classify(const float* d, int n, fdl::ConstructParams& P) {
+  double dmax = 0.0, eta = 0.0;
+  for (int k = 0; k < 32; ++k) P.d[k] = k < n ? (double)d[k] : 0.0;
+  for (int k = 0; k < n; ++k) dmax = std::fmax(dmax, std::fabs(P.d[k]));
+  for (int k1 = 0; k1 < n; ++k1)
+    for (int k2 = k1 + 1; k2 < n; ++k2)
+      eta = std::fmax(eta, std::fabs((P.d[k2] - P.d[k1]) - (P.d[k2 - k1] - P.d[0])));
+  P.eta_max = eta;
+  P.toeplitz = eta <= 1e-5 * (1.0 + dmax) ? 1 : 0;
+}
+
+}  // namespace fdl_host
 
 extern "C" {
 
@@ -108,7 +111,7 @@ int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float
   P.status = status_dev;
   P.m = m; P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F;
   P.lambda = (double)lambda; P.eps = (double)eps; P.reg = reg;
-  classify_disparities(d_host, n, P);
+  fdl_host::classify(d_host, n, P);
   trace("construct m n C F", m, n, C, (int)F);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return map_hip(n <= 16 ? fdl::launch_construct_r1(P, s) : fdl::launch_construct_r2(P, s));

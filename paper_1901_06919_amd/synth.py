@@ -199,6 +199,16 @@ def config3_instance(i: int, base_seed: int = 3000, sizes=(128, 256, 384, 512)) 
     return LightFieldSpec(layers, u, d, noise, 1e-2, 1e-3, REG_VIEW2, views, seed, f"config3[{i}]")
 
 
+def config3_shape(i: int, base_seed: int = 3000, sizes=(128, 256, 384, 512)):
+    """(grid side g, image side, layers n) of instance i -- the first three
+    draws of :func:`config3_instance`, without generating the images."""
+    rng = np.random.default_rng(base_seed + i)
+    g = int(rng.integers(3, 10))
+    side = int(rng.choice(np.asarray(sizes)))
+    n = int(rng.integers(8, 33))
+    return g, side, n
+
+
 def config5(seed: int = 5, H: int = 256, W: int = 256):
     """7x7 integer grid, 256^2, 1 channel, 16 layers linspace(-2,2,16),
     config-1 generator; returns (spec, u_init, d_init) with the start point

@@ -1,0 +1,52 @@
+"""CPU checks of the boundary: the shared library loads, exports every entry
+point include/fdl.h declares, and rejects bad arguments on the host before
+touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fdl.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(fdl_[a-z0-9_]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_1901_06919_amd as fdl
+    L = fdl.lib()
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(L, n), f"{n} declared in fdl.h but not exported"
+
+
+def test_status_strings_and_version():
+    import paper_1901_06919_amd as fdl
+    L = fdl.lib()
+    assert L.fdl_status_string(0) == b"ok"
+    assert L.fdl_status_string(-2) == b"unsupported shape"
+    assert L.fdl_version() >= 10000
+
+
+def test_host_side_validation_without_gpu():
+    import paper_1901_06919_amd as fdl
+    L = fdl.lib()
+    d = (ctypes.c_float * 4)(0, 1, 2, 3)
+    fake = ctypes.c_void_p(0x1000)
+    # n out of range, null pointers, bad sizes: rejected before any launch
+    assert L.fdl_construct(fake, fake, d, 4, 40, 1, 8, 8, 0.01, 0.001, 0, fake, None, None) == -2
+    assert L.fdl_construct(None, fake, d, 4, 4, 1, 8, 8, 0.01, 0.001, 0, fake, None, None) == -1
+    assert L.fdl_construct(fake, fake, d, 4, 4, 1, 8, 7, 0.01, 0.001, 0, fake, None, None) == -2
+    assert L.fdl_construct(fake, fake, d, 4, 4, 1, 8, 8, -1.0, 0.001, 0, fake, None, None) == -1
+    assert L.fdl_rfft2(fake, fake, 1, 8, 10, None) == -2          # W/2 = 5 unsupported
+    assert L.fdl_rfft2(fake, fake, 1, 7, 8, None) == -2           # H = 7 unsupported
+    assert L.fdl_render(fake, fake, 33, 1, 8, 8, fake, 1, fake, None) == -2
+    assert L.fdl_calib_grad(fake, fake, fake, 300, 4, 1, 8, 8, 0.01, 0.001, 1, 1, None, 0,
+                            fake, fake, fake, fake, 1 << 20, None) == -2
+    assert L.fdl_calib_workspace(49, 16, 4096) == 2048 * (1 + 98 + 16) * 8
