@@ -43,7 +43,10 @@ __global__ __launch_bounds__(256) void k_batched_flat(const ConstructParams* __r
   __shared__ TeamLds s_team[16];
   const int lane = threadIdx.x & 15;
   const int team = threadIdx.x >> 4;
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  // tiles are sorted by light-field cost, so they are NOT remapped to
+  // contiguous per-XCD ranges: the dispatcher's round-robin spreads every
+  // light field over all XCDs and keeps their loads balanced
+  const int t = blockIdx.x;
   const int lf = __builtin_amdgcn_readfirstlane(tiles[t].lf);
   const int f0 = __builtin_amdgcn_readfirstlane(tiles[t].f0);
   const ConstructParams* P = lfs + lf;

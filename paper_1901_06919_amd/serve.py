@@ -87,15 +87,24 @@ class ServeStats:
 
 class FDLServer:
     def __init__(self, pool: List[PoolEntry], hbm_budget: int = 4 << 30, max_render_batch: int = 16,
-                 max_inflight: int = 8, keep_outputs_every: int = 0):
+                 max_inflight: int = 8, keep_outputs_every: int = 0, serial: bool = False):
+        """serial=True is the plain baseline: one request at a time, in arrival
+        order, on one stream (no batching, no overlap)."""
         self.pool = pool
         self.budget = int(hbm_budget)
         self.max_render_batch = int(max_render_batch)
         self.max_inflight = int(max_inflight)
         self.keep_every = int(keep_outputs_every)
         self.dev = pool[0].view_spec.device
-        self.render_streams = [torch.cuda.Stream(device=self.dev) for _ in range(2)]
-        self.construct_stream = torch.cuda.Stream(device=self.dev)
+        if serial:
+            self.max_render_batch = 1
+            self.max_inflight = 1
+            one = torch.cuda.Stream(device=self.dev)
+            self.render_streams = [one]
+            self.construct_stream = one
+        else:
+            self.render_streams = [torch.cuda.Stream(device=self.dev) for _ in range(2)]
+            self.construct_stream = torch.cuda.Stream(device=self.dev)
         self._rr = 0
         self.kept: Dict[int, torch.Tensor] = {}
         # view parameters travel through a ring of pinned host slots (freed when
