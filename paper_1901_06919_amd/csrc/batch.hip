@@ -40,7 +40,10 @@ __device__ __forceinline__ int opaque_lane(int lane) {
 template <int CT, bool TOEP, int R>
 __global__ __launch_bounds__(256) void k_batched_flat(const ConstructParams* __restrict__ lfs,
                                                       const Tile* __restrict__ tiles) {
-  __shared__ TeamLds s_team[16];
+  __shared__ TeamLds<R> s_team[16];
+  __shared__ double2 s_tab[kPhaseTab];
+  fill_phase_table(s_tab);
+  __syncthreads();
   const int lane = threadIdx.x & 15;
   const int team = threadIdx.x >> 4;
   // tiles are sorted by light-field cost, so they are NOT remapped to
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(256) void k_batched_flat(const ConstructParams* __r
   const ConstructParams* P = lfs + lf;
   const int f = f0 + team;
   if (f >= P->F) return;
-  team_solve<R, CT, TOEP>(*P, s_team[team], f, lane);
+  team_solve<R, CT, TOEP>(*P, s_team[team], s_tab, f, lane);
 }
 
 // Persistent mode: a grid sized to the machine pulls `chunk` tiles at a time
@@ -62,8 +65,10 @@ template <int CT, bool TOEP, int R>
 __global__ __launch_bounds__(256) void k_batched_persistent(const ConstructParams* __restrict__ lfs,
                                                             const Tile* __restrict__ tiles, int ntiles, int chunk,
                                                             int* counters) {
-  __shared__ TeamLds s_team[16];
+  __shared__ TeamLds<R> s_team[16];
+  __shared__ double2 s_tab[kPhaseTab];
   __shared__ int s_tile;
+  fill_phase_table(s_tab);
   const int lane = threadIdx.x & 15;
   const int team = threadIdx.x >> 4;
   for (;;) {
@@ -78,7 +83,7 @@ __global__ __launch_bounds__(256) void k_batched_persistent(const ConstructParam
       const int f0 = __builtin_amdgcn_readfirstlane(tiles[t].f0);
       const ConstructParams* P = lfs + lf;
       const int f = f0 + team;
-      if (f < P->F) team_solve<R, CT, TOEP>(*P, s_team[team], f, opaque_lane(lane));
+      if (f < P->F) team_solve<R, CT, TOEP>(*P, s_team[team], s_tab, f, opaque_lane(lane));
     }
   }
   if (threadIdx.x == 0) {

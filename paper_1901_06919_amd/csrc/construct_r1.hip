@@ -6,12 +6,15 @@ namespace fdl {
 
 template <int R, int CT, bool TOEP>
 __global__ __launch_bounds__(256) void k_construct(ConstructParams P) {
-  __shared__ TeamLds s_team[16];
+  __shared__ TeamLds<R> s_team[16];
+  __shared__ double2 s_tab[kPhaseTab];
+  fill_phase_table(s_tab);
+  __syncthreads();
   const int lane = threadIdx.x & 15;
   const int team = threadIdx.x >> 4;
   const int f = xcd_remap(blockIdx.x, gridDim.x) * 16 + team;
   if (f >= P.F) return;
-  team_solve<R, CT, TOEP>(P, s_team[team], f, lane);
+  team_solve<R, CT, TOEP>(P, s_team[team], s_tab, f, lane);
 }
 
 template <int CT, bool TOEP>

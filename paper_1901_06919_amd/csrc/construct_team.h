@@ -7,7 +7,9 @@
 // n <= 16 R.  All arithmetic is FP64.
 //
 //   1. Views are streamed: each lane forms its own A_jk = exp(2 pi i d_k p_j)
-//      (p_j = <u_j, w>) and accumulates c_k = sum_j conj(A_jk) b_j per channel.
+//      (p_j = <u_j, w>) from a 256-entry table of exp(2 pi i t/256) and a short
+//      series for the remainder, and accumulates c_k = sum_j conj(A_jk) b_j
+//      per channel.
 //   2. The Gram matrix M = A^H A:
 //      TOEP (d an arithmetic progression up to rounding): only the first
 //        column's relatives are summed, R_q,t = sum_j p_j^q conj(A_j0) A_jt,
@@ -21,24 +23,16 @@
 //   3. M += lambda Gamma^H Gamma + eps I.
 //   4. Right-looking Cholesky M = L L^H with rows in registers; column j is
 //      broadcast with DPP row_newbcast; non-positive pivots are counted.
-//   5. Forward substitution (broadcast of y_j) and backward substitution
-//      (16-lane DPP reduction per unknown), then the layer values are stored.
+//   5. Forward substitution (broadcast of y_j); backward substitution either
+//      with a 16-lane DPP reduction per unknown (R = 1) or, for R = 2, after
+//      transposing L through LDS so that lane k holds column k of L, with a
+//      broadcast of x_i per unknown.  Then the layer values are stored.
 #pragma once
-
-#include <type_traits>
 
 #include "fdl_device.h"
 #include "fdl_internal.h"
 
 namespace fdl {
-
-template <int I, int N, typename Fn>
-__device__ __forceinline__ void static_for(Fn&& fn) {
-  if constexpr (I < N) {
-    fn(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(fn);
-  }
-}
 
 // Orders LDS traffic between the lanes of one wave (no block barrier).
 __device__ __forceinline__ void team_sync() {
@@ -59,11 +53,49 @@ __device__ __forceinline__ double layer2_gtg(int i, int k, int n) {
   return s;
 }
 
-struct TeamLds {
+// Per-block table of exp(2 pi i t / kPhaseTab), t = 0..kPhaseTab-1.
+constexpr int kPhaseTab = 256;
+
+__device__ __forceinline__ void fill_phase_table(double2* tab) {
+  for (int t = threadIdx.x; t < kPhaseTab; t += blockDim.x) {
+    double s, c;
+    sincos2pi((double)t * (1.0 / kPhaseTab), s, c);
+    tab[t] = make_double2(c, s);
+  }
+}
+
+// exp(2 pi i d p) with dt = kPhaseTab * d: the nearest table entry t = rint(dt p)
+// times exp(i x) of the remainder x = 2 pi (dt p - t) / kPhaseTab, |x| <= pi/256,
+// summed as Taylor series (sin through x^5, cos through x^6: truncation below
+// 1e-17).  dt p - t is formed by one fused multiply-add, so the phase keeps
+// full precision for any |d p| < 2^22.
+__device__ __forceinline__ cd expi_tab(const double2* __restrict__ tab, double dt, double p) {
+  const double t = rint(dt * p);
+  const double f = fma(dt, p, -t);
+  const double x = f * (kTwoPi / kPhaseTab);
+  const double x2 = x * x;
+  const double sx = fma(x * x2, fma(x2, 1.0 / 120.0, -1.0 / 6.0), x);
+  const double cx = fma(x2, fma(x2, fma(x2, -1.0 / 720.0, 1.0 / 24.0), -0.5), 1.0);
+  const double2 e = tab[(int)t & (kPhaseTab - 1)];
+  return cd{fma(e.x, cx, -e.y * sx), fma(e.y, cx, e.x * sx)};
+}
+
+struct TeamMoments {
   double d[32];
   double2 r0[32];
   float4 r12[32];
   float2 r3[32];
+};
+
+// 16 x 16 complex tile for the transposition of L (row stride 17 entries so
+// that the row-wise writes and the column-wise reads both spread over the
+// LDS banks); only the R = 2 solver uses it, after the moments are dead.
+constexpr int kTrStride = 17;
+
+template <int R>
+union TeamLds {
+  TeamMoments m;
+  double2 tr[R > 1 ? 16 * kTrStride : 1];
 };
 
 template <int R>
@@ -77,24 +109,63 @@ struct TeamRows {
   }
 };
 
+// acc -= conj(a) * x
+__device__ __forceinline__ void cfms_conja(cd& acc, cd a, cd x) {
+  acc.re = fma(-a.re, x.re, acc.re);
+  acc.re = fma(-a.im, x.im, acc.re);
+  acc.im = fma(-a.re, x.im, acc.im);
+  acc.im = fma(a.im, x.re, acc.im);
+}
+
+// In-place transposition of the strictly lower factor held by a team
+// (R = 2): on entry lane l holds rows l (L0[k] = L_{l,k}, k < 16) and l + 16
+// (L1[k] = L_{l+16,k}, k < 32); on exit it holds columns l and l + 16:
+//   L_{i,l}    = L0[i] for i < 16, L1[i - 16] for i >= 16,
+//   L_{i,l+16} = L1[i] for i >= 16.
+// Three 16 x 16 tiles pass through the team's LDS tile in the order
+// (0,0), (1,1), (1,0), which frees each register range before it is reused.
+template <int R>
+__device__ __forceinline__ void team_transpose(TeamRows<R>& S, double2* tr, int lane) {
+  auto pass = [&](auto get, auto set) {
+    team_sync();
+    static_for<0, 16>([&](auto KK) {
+      constexpr int k = decltype(KK)::value;
+      const cd v = get(std::integral_constant<int, k>{});
+      tr[lane * kTrStride + k] = make_double2(v.re, v.im);
+    });
+    team_sync();
+    static_for<0, 16>([&](auto II) {
+      constexpr int i = decltype(II)::value;
+      const double2 v = tr[i * kTrStride + lane];
+      set(std::integral_constant<int, i>{}, cd{v.x, v.y});
+    });
+  };
+  pass([&](auto k) { return S.L0[k]; }, [&](auto i, cd v) { S.L0[i] = v; });
+  pass([&](auto k) { return S.L1[16 + k]; }, [&](auto i, cd v) { S.L1[16 + i] = v; });
+  pass([&](auto k) { return S.L1[k]; }, [&](auto i, cd v) { S.L1[i] = v; });
+  team_sync();
+}
+
 template <int R, int CT, bool TOEP>
-__device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds& T, int f, int lane) {
+__device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>& T, const double2* __restrict__ tab,
+                                           int f, int lane) {
   constexpr int NMAX = 16 * R;
   const int n = P.n;
   const int C = P.C;
 
-  for (int k = lane; k < NMAX; k += 16) T.d[k] = k < n ? P.d[k] : 0.0;
+  for (int k = lane; k < NMAX; k += 16) T.m.d[k] = k < n ? P.d[k] : 0.0;
   team_sync();
 
   double wx, wy;
   bin_freq(f, P.Wh, P.H, P.W, wx, wy);
 
-  double dk[R];
+  double dk[R], dt[R];
   cd acc[R][CT];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int k = lane + 16 * r;
-    dk[r] = k < n ? T.d[k] : 0.0;
+    dk[r] = k < n ? T.m.d[k] : 0.0;
+    dt[r] = dk[r] * kPhaseTab;
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[r][c] = cd{0.0, 0.0};
   }
@@ -102,40 +173,41 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds& T,
   double pmax = 0.0;
 
   // ---- 1-2: stream the views ----
-  // The next view's position and spectra are loaded one iteration ahead so
-  // their latency overlaps the sincos work of the current view.
+  // Two view buffers, unrolled by two: the loads of view j + 1 are in flight
+  // while view j is processed.  Channels c >= C (CT > C) read channel C - 1;
+  // their sums are never stored.
   const float2* bp = P.view_spec + f;
   const size_t F = (size_t)P.F;
   const int m = P.m;
-  float2 un;
-  float2 bn[CT];
-  auto prefetch = [&](int j) {
-    un = P.u[j];
+  auto load = [&](int j, float2& u, float2 (&b)[CT]) {
+    u = P.u[j];
 #pragma unroll
-    for (int c = 0; c < CT; ++c) bn[c] = bp[((size_t)j * C + (c < C ? c : C - 1)) * F];
+    for (int c = 0; c < CT; ++c) b[c] = bp[((size_t)j * C + (c < C ? c : C - 1)) * F];
   };
-  prefetch(0);
+  cd m0[R], m1[R], m2[R], m3[R];
   if constexpr (TOEP) {
-    cd m0[R], m1[R], m2[R], m3[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) m0[r] = m1[r] = m2[r] = m3[r] = cd{0.0, 0.0};
-    for (int j = 0; j < m; ++j) {
-      const float2 uj = un;
-      float2 bc[CT];
+  } else {
+    static_for<0, R>([&](auto RR) {
+      constexpr int r = decltype(RR)::value;
 #pragma unroll
-      for (int c = 0; c < CT; ++c) bc[c] = bn[c];
-      if (j + 1 < m) prefetch(j + 1);
-      const double p = (double)uj.x * wx + (double)uj.y * wy;
+      for (int k = 0; k < 16 * (r + 1); ++k) S.template at<r>(k) = cd{0.0, 0.0};
+    });
+  }
+  auto view = [&](const float2 uj, const float2 (&bc)[CT]) {
+    const double p = fma((double)uj.x, wx, (double)uj.y * wy);
+    cd A[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) A[r] = expi_tab(tab, dt[r], p);
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const cd b = cd{(double)bc[c].x, (double)bc[c].y};
+#pragma unroll
+      for (int r = 0; r < R; ++r) cfma_conj(acc[r][c], A[r], b);
+    }
+    if constexpr (TOEP) {
       pmax = fmax(pmax, fabs(p));
-      cd A[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) A[r] = expi2pi(dk[r] * p);
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const cd b = c < C ? cd{(double)bc[c].x, (double)bc[c].y} : cd{0.0, 0.0};
-#pragma unroll
-        for (int r = 0; r < R; ++r) cfma_conj(acc[r][c], A[r], b);
-      }
       const cd a0 = bcast16<0>(A[0]);
       const double p2 = p * p, p3 = p2 * p;
 #pragma unroll
@@ -149,16 +221,41 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds& T,
         m3[r].re = fma(p3, g.re, m3[r].re);
         m3[r].im = fma(p3, g.im, m3[r].im);
       }
+    } else {
+      static_for<0, NMAX>([&](auto KK) {
+        constexpr int k = decltype(KK)::value;
+        if (k < n) {
+          const cd Ak = bcast16<k % 16>(A[k / 16]);
+          if constexpr (k < 16) cfma_conj(S.template at<0>(k), A[0], Ak);
+          if constexpr (R > 1) cfma_conj(S.template at<1>(k), A[R - 1], Ak);
+        }
+      });
     }
+  };
+  {
+    float2 ua, ub;
+    float2 ba[CT], bb[CT];
+    load(0, ua, ba);
+    int j = 0;
+    for (; j + 2 <= m; j += 2) {
+      load(j + 1, ub, bb);
+      view(ua, ba);
+      if (j + 2 < m) load(j + 2, ua, ba);
+      view(ub, bb);
+    }
+    if (j < m) view(ua, ba);
+  }
+
+  if constexpr (TOEP) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int t = lane + 16 * r;
-      T.r0[t] = make_double2(m0[r].re, m0[r].im);
-      T.r12[t] = make_float4((float)m1[r].re, (float)m1[r].im, (float)m2[r].re, (float)m2[r].im);
-      T.r3[t] = make_float2((float)m3[r].re, (float)m3[r].im);
+      T.m.r0[t] = make_double2(m0[r].re, m0[r].im);
+      T.m.r12[t] = make_float4((float)m1[r].re, (float)m1[r].im, (float)m2[r].re, (float)m2[r].im);
+      T.m.r3[t] = make_float2((float)m3[r].re, (float)m3[r].im);
     }
     team_sync();
-    const double d0 = T.d[0];
+    const double d0 = T.m.d[0];
     static_for<0, R>([&](auto RR) {
       constexpr int r = decltype(RR)::value;
       const int i = lane + 16 * r;
@@ -168,10 +265,10 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds& T,
         cd val = cd{0.0, 0.0};
         if (k <= i && i < n) {
           const int t = i - k;
-          const double2 q0 = T.r0[t];
-          const float4 q12 = T.r12[t];
-          const float2 q3 = T.r3[t];
-          const double th = kTwoPi * ((di - T.d[k]) - (T.d[t] - d0));
+          const double2 q0 = T.m.r0[t];
+          const float4 q12 = T.m.r12[t];
+          const float2 q3 = T.m.r3[t];
+          const double th = kTwoPi * ((di - T.m.d[k]) - (T.m.d[t] - d0));
           const double h2 = 0.5 * th * th;
           const double h3 = h2 * th * (1.0 / 3.0);
           const double mre = q0.x - th * (double)q12.y - h2 * (double)q12.z + h3 * (double)q3.y;
@@ -182,37 +279,6 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds& T,
       });
     });
     if (lane == 0 && P.status && kTwoPi * P.eta_max * pmax > 3e-4) atomicAdd(P.status, 1);
-  } else {
-    static_for<0, R>([&](auto RR) {
-      constexpr int r = decltype(RR)::value;
-#pragma unroll
-      for (int k = 0; k < 16 * (r + 1); ++k) S.template at<r>(k) = cd{0.0, 0.0};
-    });
-    for (int j = 0; j < m; ++j) {
-      const float2 uj = un;
-      float2 bc[CT];
-#pragma unroll
-      for (int c = 0; c < CT; ++c) bc[c] = bn[c];
-      if (j + 1 < m) prefetch(j + 1);
-      const double p = (double)uj.x * wx + (double)uj.y * wy;
-      cd A[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) A[r] = expi2pi(dk[r] * p);
-#pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const cd b = c < C ? cd{(double)bc[c].x, (double)bc[c].y} : cd{0.0, 0.0};
-#pragma unroll
-        for (int r = 0; r < R; ++r) cfma_conj(acc[r][c], A[r], b);
-      }
-      static_for<0, NMAX>([&](auto KK) {
-        constexpr int k = decltype(KK)::value;
-        if (k < n) {
-          const cd Ak = bcast16<k % 16>(A[k / 16]);
-          if constexpr (k < 16) cfma_conj(S.template at<0>(k), A[0], Ak);
-          if constexpr (R > 1) cfma_conj(S.template at<1>(k), A[R - 1], Ak);
-        }
-      });
-    }
   }
 
   // ---- 3: regulariser ----
@@ -282,13 +348,12 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds& T,
       constexpr int k = decltype(KK)::value;
       if (k >= i || i >= n) S.template at<r>(k) = cd{0.0, 0.0};
     });
-    if (i >= n) {
-#pragma unroll
-      for (int c = 0; c < CT; ++c) acc[r][c] = cd{0.0, 0.0};
-    }
   });
 
   // ---- 5a: forward substitution L y = c ----
+  // acc_j keeps c_j minus the contributions of y_0..y_{j-1}; y_j = acc_j / L_jj
+  // is broadcast from its lane and every row i > j subtracts L_ij y_j (the
+  // zeroed diagonal and upper entries leave the other rows unchanged).
   static_for<0, NMAX>([&](auto JJ) {
     constexpr int j = decltype(JJ)::value;
     if (j < n) {
@@ -308,29 +373,57 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds& T,
             acc[r][c] = t;
           }
         });
-        if (lane == oj) acc[sj][c] = yj;
       }
     }
   });
+  // y = acc / diag(L); rows >= n have invd = 0 and end as zero
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[r][c] = cscale(acc[r][c], invd[r]);
 
   // ---- 5b: backward substitution L^H x = y ----
-  static_for<0, NMAX>([&](auto II) {
-    constexpr int i = NMAX - 1 - decltype(II)::value;
-    if (i < n) {
-      constexpr int oi = i % 16, si = i / 16;
+  if constexpr (R == 1) {
+    // row layout: x_i = (y_i - sum_{k>i} conj(L_ki) x_k) / L_ii, the sum over
+    // the team's lanes by a DPP reduction
+    static_for<0, NMAX>([&](auto II) {
+      constexpr int i = NMAX - 1 - decltype(II)::value;
+      if (i < n) {
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        cd s = cd{0.0, 0.0};
-        static_for<0, R>([&](auto RR) {
-          constexpr int r = decltype(RR)::value;
-          if constexpr (i < 16 * (r + 1)) cfma_conj(s, S.template at<r>(i), acc[r][c]);
-        });
-        s.re = allreduce16(s.re);
-        s.im = allreduce16(s.im);
-        if (lane == oi) acc[si][c] = cscale(csub(acc[si][c], s), invd[si]);
+        for (int c = 0; c < CT; ++c) {
+          cd s = cd{0.0, 0.0};
+          cfma_conj(s, S.L0[i], acc[0][c]);
+          s.re = allreduce16(s.re);
+          s.im = allreduce16(s.im);
+          if (lane == i) acc[0][c] = cscale(csub(acc[0][c], s), invd[0]);
+        }
       }
-    }
-  });
+    });
+  } else {
+    // column layout: x_i = acc_i / L_ii is broadcast and every row k < i
+    // subtracts conj(L_ik) x_i; rows k >= i see zero coefficients
+    team_transpose<R>(S, T.tr, lane);
+    static_for<0, NMAX>([&](auto II) {
+      constexpr int i = NMAX - 1 - decltype(II)::value;
+      if (i < n) {
+        constexpr int oi = i % 16, si = i / 16;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          const cd xi = bcast16<oi>(cscale(acc[si][c], invd[si]));
+          if constexpr (i < 16) {
+            cfms_conja(acc[0][c], S.L0[i], xi);
+          } else {
+            cfms_conja(acc[0][c], S.L1[i - 16], xi);
+            cfms_conja(acc[1][c], S.L1[i], xi);
+          }
+        }
+      }
+    });
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < CT; ++c) acc[r][c] = cscale(acc[r][c], invd[r]);
+  }
 
   // ---- store ----
 #pragma unroll

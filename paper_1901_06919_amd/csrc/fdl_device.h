@@ -6,6 +6,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace fdl {
 
 constexpr double kPi = 3.14159265358979323846;
@@ -14,6 +16,15 @@ constexpr double kTwoPi = 6.28318530717958647692;
 struct cd {
   double re, im;
 };
+
+// Compile-time loop: fn(std::integral_constant<int, i>) for i = I .. N-1.
+template <int I, int N, typename Fn>
+__device__ __forceinline__ void static_for(Fn&& fn) {
+  if constexpr (I < N) {
+    fn(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(fn);
+  }
+}
 
 __device__ __forceinline__ cd cmake(double r, double i) { return cd{r, i}; }
 __device__ __forceinline__ cd cadd(cd a, cd b) { return cd{a.re + b.re, a.im + b.im}; }

@@ -41,6 +41,30 @@ __device__ __forceinline__ float2 twiddle(float r) {
   return make_float2(__builtin_amdgcn_cosf(r), __builtin_amdgcn_sinf(r));
 }
 
+// In-place DFT of R = 2, 3 or 4 values (forward sign -, inverse +).
+template <int R, bool INV>
+__device__ __forceinline__ void butterfly(float2 (&v)[R]) {
+  if constexpr (R == 4) {
+    const float2 a0 = f2add(v[0], v[2]), a1 = f2sub(v[0], v[2]);
+    const float2 a2 = f2add(v[1], v[3]), a3 = rot90<INV>(f2sub(v[1], v[3]));
+    v[0] = f2add(a0, a2);
+    v[2] = f2sub(a0, a2);
+    v[1] = f2add(a1, a3);
+    v[3] = f2sub(a1, a3);
+  } else if constexpr (R == 2) {
+    const float2 a0 = v[0];
+    v[0] = f2add(a0, v[1]);
+    v[1] = f2sub(a0, v[1]);
+  } else {   // R == 3
+    const float2 t1 = f2add(v[1], v[2]);
+    const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
+    const float2 s = f2scale(rot90<INV>(f2sub(v[1], v[2])), 0.86602540378443864676f);
+    v[0] = f2add(v[0], t1);
+    v[1] = f2add(t2, s);
+    v[2] = f2sub(t2, s);
+  }
+}
+
 // One Stockham stage of radix R over a length-N sequence held in LDS.
 template <int R, bool INV>
 __device__ __forceinline__ void stockham_stage(const float2* __restrict__ in, float2* __restrict__ out, int N, int Ns,
@@ -58,25 +82,7 @@ __device__ __forceinline__ void stockham_stage(const float2* __restrict__ in, fl
 #pragma unroll
       for (int r = 1; r < R; ++r) v[r] = f2mul(v[r], twiddle(a * (float)r));
     }
-    if constexpr (R == 4) {
-      const float2 a0 = f2add(v[0], v[2]), a1 = f2sub(v[0], v[2]);
-      const float2 a2 = f2add(v[1], v[3]), a3 = rot90<INV>(f2sub(v[1], v[3]));
-      v[0] = f2add(a0, a2);
-      v[2] = f2sub(a0, a2);
-      v[1] = f2add(a1, a3);
-      v[3] = f2sub(a1, a3);
-    } else if constexpr (R == 2) {
-      const float2 a0 = v[0];
-      v[0] = f2add(a0, v[1]);
-      v[1] = f2sub(a0, v[1]);
-    } else {   // R == 3
-      const float2 t1 = f2add(v[1], v[2]);
-      const float2 t2 = make_float2(v[0].x - 0.5f * t1.x, v[0].y - 0.5f * t1.y);
-      const float2 s = f2scale(rot90<INV>(f2sub(v[1], v[2])), 0.86602540378443864676f);
-      v[0] = f2add(v[0], t1);
-      v[1] = f2add(t2, s);
-      v[2] = f2sub(t2, s);
-    }
+    butterfly<R, INV>(v);
     const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) out[base + r * Ns] = v[r];
@@ -102,6 +108,152 @@ __device__ __forceinline__ float2* lds_fft(float2* b0, float2* b1, const FftPlan
     out = tmp;
   }
   return in;
+}
+
+// ---- register-resident transforms (compile-time length) ---------------------
+
+// cos and sin of 2 pi a / b at compile time (series after reduction to
+// [-pi, pi]; converged to double precision).
+constexpr double ct_rev_series(long a, long b, bool want_sin) {
+  a %= b;
+  if (a < 0) a += b;
+  if (2 * a > b) a -= b;
+  const double x = 6.28318530717958647692 * (double)a / (double)b;
+  double term = want_sin ? x : 1.0, sum = term;
+  for (int i = 1; i < 40; ++i) {
+    const double d = want_sin ? (double)(2 * i) * (2 * i + 1) : (double)(2 * i - 1) * (2 * i);
+    term *= -x * x / d;
+    sum += term;
+  }
+  return sum;
+}
+
+// Stockham stages over a register array (every index is a compile-time
+// constant, so the stages compile to straight-line code).  Radix 4 while it
+// divides the remaining length, then 2, then 3; the same stage formula as
+// the LDS version above.
+template <int N, int Ns, bool INV>
+__device__ __forceinline__ void reg_fft_from(float2 (&a)[N]) {
+  if constexpr (Ns < N) {
+    constexpr int rem = N / Ns;
+    constexpr int R = rem % 4 == 0 ? 4 : (rem % 2 == 0 ? 2 : 3);
+    static_assert(rem % R == 0, "length must be 2^a 3^b");
+    float2 b[N];
+    static_for<0, N / R>([&](auto JJ) {
+      constexpr int j = decltype(JJ)::value;
+      constexpr int k = j % Ns;
+      float2 v[R];
+      static_for<0, R>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        v[r] = a[j + r * (N / R)];
+        if constexpr (k * r != 0) {
+          constexpr long num = INV ? (long)k * r : -(long)k * r;
+          constexpr float wr = (float)ct_rev_series(num, (long)Ns * R, false);
+          constexpr float wi = (float)ct_rev_series(num, (long)Ns * R, true);
+          v[r] = f2mul(v[r], make_float2(wr, wi));
+        }
+      });
+      butterfly<R, INV>(v);
+      constexpr int base = (j / Ns) * Ns * R + k;
+      static_for<0, R>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        b[base + r * Ns] = v[r];
+      });
+    });
+    reg_fft_from<N, Ns * R, INV>(b);
+    static_for<0, N>([&](auto II) {
+      constexpr int i = decltype(II)::value;
+      a[i] = b[i];
+    });
+  }
+}
+
+template <int N, bool INV>
+__device__ __forceinline__ void reg_fft(float2 (&a)[N]) {
+  reg_fft_from<N, 1, INV>(a);
+}
+
+// ---- columns, register four-step version ---------------------------------------
+// Length H = P Q with Q a multiple of P; a block transforms TC adjacent
+// columns with P threads per column.  With y = t + P q and k = k1 + Q k2,
+//   X[k1 + Q k2] = sum_t W_P^{t k2} W_H^{t k1} sum_q x[t + P q] W_Q^{q k1},
+// so thread t (1) loads x[t + P q], q < Q, (2) transforms them in registers
+// (length Q), (3) multiplies by W_H^{t k1}, (4) passes the Q values through
+// LDS, (5) takes Q/P of the k1 rows and transforms each over t in registers
+// (length P), (6) stores X[k1 + Q k2].  Loads and stores of a wave cover whole
+// 128-byte row segments (16 columns x 8 bytes); the LDS tile uses padded
+// strides (k1 stride P + 1, column stride = 4 mod 32 entries) so that both
+// access patterns spread over the banks.
+template <int P, int Q, int TC, bool INV>
+__global__ __launch_bounds__(TC * P) void k_fft_cols_reg(float2* __restrict__ data, int Wh, int tiles) {
+  static_assert(Q % P == 0, "Q must be a multiple of P");
+  constexpr int H = P * Q;
+  constexpr int KS = P + 1;
+  constexpr int CS0 = Q * KS;
+  constexpr int CS = CS0 + ((36 - CS0 % 32) % 32);
+  __shared__ float2 lds[TC * CS];
+  const int img = blockIdx.x / tiles;
+  const int c0 = (blockIdx.x - img * tiles) * TC;
+  const int col = threadIdx.x % TC;
+  const int t = threadIdx.x / TC;
+  const bool live = c0 + col < Wh;
+  float2* base = data + (size_t)img * H * Wh + c0 + col;
+  float2 v[Q];
+  static_for<0, Q>([&](auto QQ) {
+    constexpr int q = decltype(QQ)::value;
+    v[q] = live ? base[(size_t)(t + P * q) * Wh] : make_float2(0.0f, 0.0f);
+  });
+  reg_fft<Q, INV>(v);
+  const float step = (INV ? 1.0f : -1.0f) * (float)t * (1.0f / (float)H);
+  static_for<1, Q>([&](auto KK) {
+    constexpr int k1 = decltype(KK)::value;
+    v[k1] = f2mul(v[k1], twiddle(step * (float)k1));
+  });
+  float2* mine = lds + col * CS;
+  static_for<0, Q>([&](auto KK) {
+    constexpr int k1 = decltype(KK)::value;
+    mine[k1 * KS + t] = v[k1];
+  });
+  __syncthreads();
+  static_for<0, Q / P>([&](auto SS) {
+    constexpr int s = decltype(SS)::value;
+    const int k1 = t + P * s;
+    float2 w[P];
+    static_for<0, P>([&](auto PP) {
+      constexpr int p = decltype(PP)::value;
+      w[p] = mine[k1 * KS + p];
+    });
+    reg_fft<P, INV>(w);
+    if (live) {
+      static_for<0, P>([&](auto KK) {
+        constexpr int k2 = decltype(KK)::value;
+        base[(size_t)(k1 + Q * k2) * Wh] = w[k2];
+      });
+    }
+  });
+}
+
+template <int P, int Q, int TC, bool INV>
+static hipError_t go_cols_reg(float2* data, int batch, int Wh, hipStream_t s) {
+  const int tiles = (Wh + TC - 1) / TC;
+  hipLaunchKernelGGL((k_fft_cols_reg<P, Q, TC, INV>), dim3(batch * tiles), dim3(TC * P), 0, s, data, Wh, tiles);
+  return hipGetLastError();
+}
+
+// Register kernel for the column lengths it is instantiated for; false for
+// the others (the LDS Stockham kernel below takes them).
+template <bool INV>
+static bool cols_reg(float2* data, int batch, int H, int Wh, hipStream_t s, hipError_t& err) {
+  switch (H) {
+    case 64: err = go_cols_reg<8, 8, 16, INV>(data, batch, Wh, s); return true;
+    case 128: err = go_cols_reg<8, 16, 16, INV>(data, batch, Wh, s); return true;
+    case 256: err = go_cols_reg<16, 16, 16, INV>(data, batch, Wh, s); return true;
+    case 384: err = go_cols_reg<8, 48, 16, INV>(data, batch, Wh, s); return true;
+    case 512: err = go_cols_reg<16, 32, 16, INV>(data, batch, Wh, s); return true;
+    case 768: err = go_cols_reg<16, 48, 8, INV>(data, batch, Wh, s); return true;
+    case 1024: err = go_cols_reg<32, 32, 8, INV>(data, batch, Wh, s); return true;
+    default: return false;
+  }
 }
 
 // ---- forward rows: real rows -> half spectra --------------------------------
@@ -243,6 +395,8 @@ hipError_t launch_rfft2(const FftParams& P, hipStream_t s) {
   // columns
   {
     const int H = P.H, Wh = N + 1;
+    hipError_t e = hipSuccess;
+    if (cols_reg<false>(P.cplx, P.batch, H, Wh, s, e)) return e;
     const int TC = P.col_tc;
     const int G = 256 / TC;
     const int tiles = (Wh + TC - 1) / TC;
@@ -258,14 +412,17 @@ hipError_t launch_irfft2(const FftParams& P, hipStream_t s) {
   const int N = P.W / 2;
   {
     const int H = P.H, Wh = N + 1;
-    const int TC = P.col_tc;
-    const int G = 256 / TC;
-    const int tiles = (Wh + TC - 1) / TC;
-    const size_t lds = (size_t)TC * (2 * H + 1) * sizeof(float2);
-    opt_in_lds<true>(lds);
-    hipLaunchKernelGGL(k_fft_cols<true>, dim3(P.batch * tiles), dim3(TC * G), lds, s, P.cplx, P.batch, H, Wh,
-                       tiles, P.col_plan, G, TC);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipSuccess;
+    if (!cols_reg<true>(P.cplx, P.batch, H, Wh, s, e)) {
+      const int TC = P.col_tc;
+      const int G = 256 / TC;
+      const int tiles = (Wh + TC - 1) / TC;
+      const size_t lds = (size_t)TC * (2 * H + 1) * sizeof(float2);
+      opt_in_lds<true>(lds);
+      hipLaunchKernelGGL(k_fft_cols<true>, dim3(P.batch * tiles), dim3(TC * G), lds, s, P.cplx, P.batch, H, Wh,
+                         tiles, P.col_plan, G, TC);
+      e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
   }
   {
