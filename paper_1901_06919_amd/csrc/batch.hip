@@ -38,7 +38,7 @@ __device__ __forceinline__ int opaque_lane(int lane) {
 // Flat modes: one block per tile.  R is the row-slot class of the launch
 // (R = 2 also solves n <= 16, so a single launch can cover every light field).
 template <int CT, bool TOEP, int R>
-__global__ __launch_bounds__(256) void k_batched_flat(const ConstructParams* __restrict__ lfs,
+__global__ __launch_bounds__(256, TOEP && R > 1 ? 2 : 1) void k_batched_flat(const ConstructParams* __restrict__ lfs,
                                                       const Tile* __restrict__ tiles) {
   __shared__ TeamLds<R> s_team[16];
   __shared__ double2 s_tab[kPhaseTab];

@@ -5,7 +5,7 @@
 namespace fdl {
 
 template <int R, int CT, bool TOEP>
-__global__ __launch_bounds__(256) void k_construct(ConstructParams P) {
+__global__ __launch_bounds__(256, TOEP ? 2 : 1) void k_construct(ConstructParams P) {
   __shared__ TeamLds<R> s_team[16];
   __shared__ double2 s_tab[kPhaseTab];
   fill_phase_table(s_tab);

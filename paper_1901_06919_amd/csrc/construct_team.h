@@ -41,18 +41,6 @@ __device__ __forceinline__ void team_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// (Gamma^T Gamma)_{ik} for Gamma = tridiag(1,-2,1) of size n (Eq. 2ndOrderLayer).
-__device__ __forceinline__ double layer2_gtg(int i, int k, int n) {
-  double s = 0.0;
-  for (int p = i - 1; p <= i + 1; ++p) {
-    if (p < 0 || p >= n) continue;
-    const int a = p - i, b = p - k;
-    if (b < -1 || b > 1) continue;
-    s += (a == 0 ? -2.0 : 1.0) * (b == 0 ? -2.0 : 1.0);
-  }
-  return s;
-}
-
 // Per-block table of exp(2 pi i t / kPhaseTab), t = 0..kPhaseTab-1.
 constexpr int kPhaseTab = 256;
 
@@ -80,11 +68,18 @@ __device__ __forceinline__ cd expi_tab(const double2* __restrict__ tab, double d
   return cd{fma(e.x, cx, -e.y * sx), fma(e.y, cx, e.x * sx)};
 }
 
+// R0 in FP64; R1..R3 only enter through the residue corrections (|th| below
+// about 1e-5), where FP32 keeps the entries exact to FP64 rounding.
 struct TeamMoments {
   double d[32];
   double2 r0[32];
   float4 r12[32];
   float2 r3[32];
+};
+
+// right-hand sides parked in LDS during the factorisation (lane-major)
+struct TeamRhs {
+  double2 c[16][8];
 };
 
 // 16 x 16 complex tile for the transposition of L (row stride 17 entries so
@@ -95,6 +90,7 @@ constexpr int kTrStride = 17;
 template <int R>
 union TeamLds {
   TeamMoments m;
+  TeamRhs rhs;
   double2 tr[R > 1 ? 16 * kTrStride : 1];
 };
 
@@ -108,6 +104,16 @@ struct TeamRows {
     else return L1[k];
   }
 };
+
+// Ends a scheduling region: the unrolled solver is one basic block, and
+// without these fences the scheduler hoists loads and broadcasts of later
+// steps far enough to exceed the register budget.
+__device__ __forceinline__ void sched_fence() { __builtin_amdgcn_sched_barrier(0); }
+
+// Pins the computation of v at this point (an empty asm that reads and
+// writes it): keeps the compiler from sinking the assembly arithmetic to the
+// first use of each entry while its LDS operands stay live in between.
+__device__ __forceinline__ void pin(cd& v) { asm volatile("" : "+v"(v.re), "+v"(v.im)); }
 
 // acc -= conj(a) * x
 __device__ __forceinline__ void cfms_conja(cd& acc, cd a, cd x) {
@@ -149,6 +155,10 @@ __device__ __forceinline__ void team_transpose(TeamRows<R>& S, double2* tr, int 
 template <int R, int CT, bool TOEP>
 __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>& T, const double2* __restrict__ tab,
                                            int f, int lane) {
+  // The system is padded to NMAX = 16 R unknowns with an identity block
+  // (rows and columns >= n), so that every unrolled step below runs without
+  // a branch on n: the padded unknowns have zero right-hand sides and solve
+  // to zero without touching the others.
   constexpr int NMAX = 16 * R;
   const int n = P.n;
   const int C = P.C;
@@ -173,14 +183,18 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   double pmax = 0.0;
 
   // ---- 1-2: stream the views ----
-  // Two view buffers, unrolled by two: the loads of view j + 1 are in flight
-  // while view j is processed.  Channels c >= C (CT > C) read channel C - 1;
-  // their sums are never stored.
+  // Channels c >= C (CT > C) read channel C - 1; their sums are never stored.
   const float2* bp = P.view_spec + f;
   const size_t F = (size_t)P.F;
   const int m = P.m;
+  // u is read through a lane-varying (zero) offset so that it travels as a
+  // vector load: a scalar load would share its wait counter with the LDS
+  // table reads and stall every one of them.
+  int vzero;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+  const float2* up = P.u + vzero;
   auto load = [&](int j, float2& u, float2 (&b)[CT]) {
-    u = P.u[j];
+    u = up[j];
 #pragma unroll
     for (int c = 0; c < CT; ++c) b[c] = bp[((size_t)j * C + (c < C ? c : C - 1)) * F];
   };
@@ -224,27 +238,78 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
     } else {
       static_for<0, NMAX>([&](auto KK) {
         constexpr int k = decltype(KK)::value;
-        if (k < n) {
-          const cd Ak = bcast16<k % 16>(A[k / 16]);
-          if constexpr (k < 16) cfma_conj(S.template at<0>(k), A[0], Ak);
-          if constexpr (R > 1) cfma_conj(S.template at<1>(k), A[R - 1], Ak);
-        }
+        const cd Ak = bcast16<k % 16>(A[k / 16]);
+        if constexpr (k < 16) cfma_conj(S.template at<0>(k), A[0], Ak);
+        if constexpr (R > 1) cfma_conj(S.template at<1>(k), A[R - 1], Ak);
       });
     }
   };
   {
-    float2 ua, ub;
-    float2 ba[CT], bb[CT];
+    // three view buffers in rotation: the loads of a view are issued two
+    // views before it is processed.  The prefetch index is clamped instead of
+    // guarded, so that every load is unconditional and each wait can name the
+    // oldest batch only (a guarded load forces waits for all loads in flight).
+    float2 ua, ub, uc;
+    float2 ba[CT], bb[CT], bc[CT];
+    const int last = m - 1;
     load(0, ua, ba);
+    load(min(1, last), ub, bb);
     int j = 0;
-    for (; j + 2 <= m; j += 2) {
-      load(j + 1, ub, bb);
+    for (; j + 3 <= m; j += 3) {
+      load(j + 2, uc, bc);
       view(ua, ba);
-      if (j + 2 < m) load(j + 2, ua, ba);
+      load(min(j + 3, last), ua, ba);
       view(ub, bb);
+      load(min(j + 4, last), ub, bb);
+      view(uc, bc);
     }
     if (j < m) view(ua, ba);
+    if (j + 1 < m) view(ub, bb);
   }
+  // padded rows get zero right-hand sides
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const bool live = lane + 16 * r < n;
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[r][c] = live ? acc[r][c] : cd{0.0, 0.0};
+  }
+
+  // ---- 3: regulariser (bands of lambda Gamma^H Gamma + eps I) ----
+  // diagonal per row: VIEW2 lambda |w|^4 d_i^4, LAYER2 lambda (4 + [i > 0] +
+  // [i < n - 1]), L2 lambda; plus eps.  LAYER2 also has -4 lambda on the first
+  // and lambda on the second sub-diagonal (the same in every row).
+  double diag[R];
+  {
+    const double w2 = wx * wx + wy * wy;
+    const double w4 = w2 * w2;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = lane + 16 * r;
+      double g;
+      if (P.reg == 0) {
+        const double d2 = dk[r] * dk[r];
+        g = P.lambda * w4 * d2 * d2;
+      } else if (P.reg == 1) {
+        g = P.lambda * (4.0 + (i > 0 ? 1.0 : 0.0) + (i < n - 1 ? 1.0 : 0.0));
+      } else {
+        g = P.lambda;
+      }
+      diag[r] = g + P.eps;
+    }
+  }
+  const double sub1 = P.reg == 1 ? -4.0 * P.lambda : 0.0;
+  const double sub2 = P.reg == 1 ? P.lambda : 0.0;
+  // entry (i, k = i - t) of the padded lower triangle from the Gram value
+  auto entry = [&](int t, int i, double dg, double gre, double gim) -> cd {
+    const bool live = (t >= 0) & (i < n);
+    double band = t == 2 ? sub2 : 0.0;
+    band = t == 1 ? sub1 : band;
+    band = t == 0 ? dg : band;
+    const double pad = t == 0 ? 1.0 : 0.0;
+    const double re = live ? gre + band : pad;
+    const double im = live & (t != 0) ? gim : 0.0;
+    return cd{re, im};
+  };
 
   if constexpr (TOEP) {
 #pragma unroll
@@ -262,50 +327,43 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
       const double di = dk[r];
       static_for<0, 16 * (r + 1)>([&](auto KK) {
         constexpr int k = decltype(KK)::value;
-        cd val = cd{0.0, 0.0};
-        if (k <= i && i < n) {
-          const int t = i - k;
-          const double2 q0 = T.m.r0[t];
-          const float4 q12 = T.m.r12[t];
-          const float2 q3 = T.m.r3[t];
-          const double th = kTwoPi * ((di - T.m.d[k]) - (T.m.d[t] - d0));
-          const double h2 = 0.5 * th * th;
-          const double h3 = h2 * th * (1.0 / 3.0);
-          const double mre = q0.x - th * (double)q12.y - h2 * (double)q12.z + h3 * (double)q3.y;
-          const double mim = q0.y + th * (double)q12.x - h2 * (double)q12.w - h3 * (double)q3.x;
-          val = cd{mre, -mim};   // M_{i,k} = conj(M_{k,i})
-        }
-        S.template at<r>(k) = val;
+        const int t = i - k;
+        const int tc = t < 0 ? 0 : t;
+        const double2 q0 = T.m.r0[tc];
+        const float4 q12 = T.m.r12[tc];
+        const float2 q3 = T.m.r3[tc];
+        const double th = kTwoPi * ((di - T.m.d[k]) - (T.m.d[tc] - d0));
+        const double h2 = 0.5 * th * th;
+        const double h3 = h2 * th * (1.0 / 3.0);
+        // M_{k,i} = R0 + i th R1 - th^2/2 R2 - i th^3/6 R3;  M_{i,k} = conj(M_{k,i})
+        const double mre = q0.x - th * (double)q12.y - h2 * (double)q12.z + h3 * (double)q3.y;
+        const double mim = q0.y + th * (double)q12.x - h2 * (double)q12.w - h3 * (double)q3.x;
+        cd e = entry(t, i, diag[r], mre, -mim);
+        pin(e);
+        S.template at<r>(k) = e;
       });
     });
     if (lane == 0 && P.status && kTwoPi * P.eta_max * pmax > 3e-4) atomicAdd(P.status, 1);
-  }
-
-  // ---- 3: regulariser ----
-  {
-    const double w2 = wx * wx + wy * wy;
-    const double w4 = w2 * w2;
+  } else {
     static_for<0, R>([&](auto RR) {
       constexpr int r = decltype(RR)::value;
       const int i = lane + 16 * r;
       static_for<0, 16 * (r + 1)>([&](auto KK) {
         constexpr int k = decltype(KK)::value;
-        if (i < n && k <= i && i - k <= 2) {
-          double add = 0.0;
-          if (P.reg == 0) {
-            if (k == i) { const double d2 = dk[r] * dk[r]; add = P.lambda * w4 * d2 * d2; }
-          } else if (P.reg == 1) {
-            add = P.lambda * layer2_gtg(i, k, n);
-          } else if (k == i) {
-            add = P.lambda;
-          }
-          if (k == i) add += P.eps;
-          S.template at<r>(k).re += add;
-        }
-        if (k == i) S.template at<r>(k).im = 0.0;
+        const cd g = S.template at<r>(k);
+        cd e = entry(i - k, i, diag[r], g.re, g.im);
+        pin(e);
+        S.template at<r>(k) = e;
       });
     });
   }
+
+  // the right-hand sides wait in LDS while the factorisation holds the registers
+  team_sync();
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) T.rhs.c[lane][r * CT + c] = make_double2(acc[r][c].re, acc[r][c].im);
 
   // ---- 4: Cholesky ----
   bool bad = false;
@@ -314,41 +372,49 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   for (int r = 0; r < R; ++r) invd[r] = 0.0;
   static_for<0, NMAX>([&](auto JJ) {
     constexpr int j = decltype(JJ)::value;
-    if (j < n) {
-      constexpr int oj = j % 16, sj = j / 16;
-      double piv = bcast16<oj>(S.template at<sj>(j).re);
-      if (!(piv > 0.0) || !isfinite(piv)) { bad = true; piv = 1e-300; }
-      double y = __builtin_amdgcn_rsq(piv);
-      y = y * fma(-0.5 * piv * y, y, 1.5);
-      y = y * fma(-0.5 * piv * y, y, 1.5);
-      if (lane == oj) invd[sj] = y;
+    constexpr int oj = j % 16, sj = j / 16;
+    double piv = bcast16<oj>(S.template at<sj>(j).re);
+    const bool ok = piv > 0.0 && isfinite(piv);
+    bad = bad || !ok;
+    piv = ok ? piv : 1e-300;
+    double y = __builtin_amdgcn_rsq(piv);
+    y = y * fma(-0.5 * piv * y, y, 1.5);
+    y = y * fma(-0.5 * piv * y, y, 1.5);
+    invd[sj] = lane == oj ? y : invd[sj];
+    static_for<0, R>([&](auto RR) {
+      constexpr int r = decltype(RR)::value;
+      if constexpr (j < 16 * (r + 1)) S.template at<r>(j) = cscale(S.template at<r>(j), y);
+    });
+    static_for<j + 1, NMAX>([&](auto KK) {
+      constexpr int k = decltype(KK)::value;
+      const cd Lkj = bcast16<k % 16>(S.template at<k / 16>(j));
       static_for<0, R>([&](auto RR) {
         constexpr int r = decltype(RR)::value;
-        if constexpr (j < 16 * (r + 1)) S.template at<r>(j) = cscale(S.template at<r>(j), y);
+        if constexpr (k < 16 * (r + 1)) cfms_aconjb(S.template at<r>(k), S.template at<r>(j), Lkj);
       });
-      static_for<j + 1, NMAX>([&](auto KK) {
-        constexpr int k = decltype(KK)::value;
-        if (k < n) {
-          const cd Lkj = bcast16<k % 16>(S.template at<k / 16>(j));
-          static_for<0, R>([&](auto RR) {
-            constexpr int r = decltype(RR)::value;
-            if constexpr (k < 16 * (r + 1)) cfms_aconjb(S.template at<r>(k), S.template at<r>(j), Lkj);
-          });
-        }
-      });
-    }
+    });
+    sched_fence();
   });
   if (bad && lane == 0 && P.status) atomicAdd(P.status, 1);
 
-  // strictly lower part only; rows >= n are empty
+  // strictly lower part only (the padded rows are already zero off the diagonal)
   static_for<0, R>([&](auto RR) {
     constexpr int r = decltype(RR)::value;
     const int i = lane + 16 * r;
     static_for<0, 16 * (r + 1)>([&](auto KK) {
       constexpr int k = decltype(KK)::value;
-      if (k >= i || i >= n) S.template at<r>(k) = cd{0.0, 0.0};
+      const cd v = S.template at<r>(k);
+      S.template at<r>(k) = k < i ? v : cd{0.0, 0.0};
     });
   });
+
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) {
+      const double2 v = T.rhs.c[lane][r * CT + c];
+      acc[r][c] = cd{v.x, v.y};
+    }
 
   // ---- 5a: forward substitution L y = c ----
   // acc_j keeps c_j minus the contributions of y_0..y_{j-1}; y_j = acc_j / L_jj
@@ -356,27 +422,26 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   // zeroed diagonal and upper entries leave the other rows unchanged).
   static_for<0, NMAX>([&](auto JJ) {
     constexpr int j = decltype(JJ)::value;
-    if (j < n) {
-      constexpr int oj = j % 16, sj = j / 16;
+    constexpr int oj = j % 16, sj = j / 16;
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        const cd yj = bcast16<oj>(cscale(acc[sj][c], invd[sj]));
-        static_for<0, R>([&](auto RR) {
-          constexpr int r = decltype(RR)::value;
-          if constexpr (j < 16 * (r + 1)) {
-            cd t = acc[r][c];
-            const cd l = S.template at<r>(j);
-            t.re = fma(-l.re, yj.re, t.re);
-            t.re = fma(l.im, yj.im, t.re);
-            t.im = fma(-l.re, yj.im, t.im);
-            t.im = fma(-l.im, yj.re, t.im);
-            acc[r][c] = t;
-          }
-        });
-      }
+    for (int c = 0; c < CT; ++c) {
+      const cd yj = bcast16<oj>(cscale(acc[sj][c], invd[sj]));
+      static_for<0, R>([&](auto RR) {
+        constexpr int r = decltype(RR)::value;
+        if constexpr (j < 16 * (r + 1)) {
+          cd t = acc[r][c];
+          const cd l = S.template at<r>(j);
+          t.re = fma(-l.re, yj.re, t.re);
+          t.re = fma(l.im, yj.im, t.re);
+          t.im = fma(-l.re, yj.im, t.im);
+          t.im = fma(-l.im, yj.re, t.im);
+          acc[r][c] = t;
+        }
+      });
     }
+    sched_fence();
   });
-  // y = acc / diag(L); rows >= n have invd = 0 and end as zero
+  // y = acc / diag(L)
 #pragma unroll
   for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -388,16 +453,16 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
     // the team's lanes by a DPP reduction
     static_for<0, NMAX>([&](auto II) {
       constexpr int i = NMAX - 1 - decltype(II)::value;
-      if (i < n) {
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          cd s = cd{0.0, 0.0};
-          cfma_conj(s, S.L0[i], acc[0][c]);
-          s.re = allreduce16(s.re);
-          s.im = allreduce16(s.im);
-          if (lane == i) acc[0][c] = cscale(csub(acc[0][c], s), invd[0]);
-        }
+      for (int c = 0; c < CT; ++c) {
+        cd s = cd{0.0, 0.0};
+        cfma_conj(s, S.L0[i], acc[0][c]);
+        s.re = allreduce16(s.re);
+        s.im = allreduce16(s.im);
+        const cd xi = cscale(csub(acc[0][c], s), invd[0]);
+        acc[0][c] = lane == i ? xi : acc[0][c];
       }
+      sched_fence();
     });
   } else {
     // column layout: x_i = acc_i / L_ii is broadcast and every row k < i
@@ -405,19 +470,18 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
     team_transpose<R>(S, T.tr, lane);
     static_for<0, NMAX>([&](auto II) {
       constexpr int i = NMAX - 1 - decltype(II)::value;
-      if (i < n) {
-        constexpr int oi = i % 16, si = i / 16;
+      constexpr int oi = i % 16, si = i / 16;
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          const cd xi = bcast16<oi>(cscale(acc[si][c], invd[si]));
-          if constexpr (i < 16) {
-            cfms_conja(acc[0][c], S.L0[i], xi);
-          } else {
-            cfms_conja(acc[0][c], S.L1[i - 16], xi);
-            cfms_conja(acc[1][c], S.L1[i], xi);
-          }
+      for (int c = 0; c < CT; ++c) {
+        const cd xi = bcast16<oi>(cscale(acc[si][c], invd[si]));
+        if constexpr (i < 16) {
+          cfms_conja(acc[0][c], S.L0[i], xi);
+        } else {
+          cfms_conja(acc[0][c], S.L1[i - 16], xi);
+          cfms_conja(acc[1][c], S.L1[i], xi);
         }
       }
+      sched_fence();
     });
 #pragma unroll
     for (int r = 0; r < R; ++r)

@@ -2,10 +2,11 @@
 //   B_v(w) = sum_k exp(+2 pi i d_k <u0_v, w>) psi_hat_v((s_v - d_k) w) L_k(w)
 // for a batch of V views sharing one pass over the layers.
 //
-// One thread per half-spectrum bin and a chunk of VB views (grid.y over
-// chunks): the layer values of the bin are loaded once per chunk (coalesced
-// along the bin index), every view of the chunk accumulates in registers.
-// FP32 arithmetic: rendering is a plain weighted sum, no ill-conditioning.
+// One thread per half-spectrum bin and a chunk of VB views: the layer values
+// of the bin are loaded once per chunk (coalesced along the bin index), every
+// view of the chunk accumulates in registers; the disk aperture spectrum
+// 2 J1(z)/z comes from a per-block LDS table of cubic pieces.  FP32
+// arithmetic: rendering is a plain weighted sum, no ill-conditioning.
 #include "fdl_device.h"
 #include "fdl_internal.h"
 
@@ -65,43 +66,83 @@ __device__ __forceinline__ float jinc2(float z) {
   return 2.0f * j1 / z;
 }
 
-// sin(pi t) / (pi t)
-__device__ __forceinline__ float sincf(float t) {
-  if (fabsf(t) < 1e-4f) {
-    const float a = (float)kPi * t;
-    return 1.0f - a * a * (1.0f / 6.0f);
-  }
-  const float h = 0.5f * t;                       // revolutions of pi t
-  const float s = __builtin_amdgcn_sinf(h - rintf(h));
-  return s / ((float)kPi * t);
+// sin(pi t) / (pi t) with a hardware reciprocal (about 1 ulp)
+__device__ __forceinline__ float sinc_fast(float t) {
+  const float a = (float)kPi * t;
+  if (fabsf(t) < 1e-4f) return 1.0f - a * a * (1.0f / 6.0f);
+  const float h = 0.5f * t;   // revolutions of pi t
+  return __builtin_amdgcn_sinf(h - rintf(h)) * __builtin_amdgcn_rcpf(a);
 }
 
-__device__ __forceinline__ float psi_hat_f(int shape, float rho, float xx, float xy) {
-  if (rho == 0.0f) return 1.0f;
-  if (shape == 1) {
-    const float z = (float)kTwoPi * rho * sqrtf(xx * xx + xy * xy);
-    return jinc2(z);
+// ---- tabulated 2 J1(z) / z --------------------------------------------------
+// Cubic pieces on [i h, (i + 1) h], i < kJincN, through the four nodes
+// (i-1) h .. (i+2) h (the function is even, so node -h is node h), in the
+// local variable t = z / h - i; nodes from jinc2 above.  Interpolation error
+// below 1e-6 for h = 1/8 (fourth derivative at most 1/8); beyond kJincN h the
+// asymptotic form is evaluated directly.
+constexpr int kJincN = 1024;
+constexpr float kJincH = 0.125f;
+
+__device__ __forceinline__ void build_jinc_table(float4* tab, float* nodes) {
+  for (int i = threadIdx.x; i < kJincN + 3; i += blockDim.x) nodes[i] = jinc2(fabsf((float)(i - 1) * kJincH));
+  __syncthreads();
+  for (int i = threadIdx.x; i < kJincN; i += blockDim.x) {
+    const float fm = nodes[i], f0 = nodes[i + 1], f1 = nodes[i + 2], f2 = nodes[i + 3];
+    tab[i] = make_float4(f0, (-2.0f * fm - 3.0f * f0 + 6.0f * f1 - f2) * (1.0f / 6.0f), 0.5f * (fm - 2.0f * f0 + f1),
+                         (-fm + 3.0f * f0 - 3.0f * f1 + f2) * (1.0f / 6.0f));
   }
-  if (shape == 2) return sincf(2.0f * rho * xx) * sincf(2.0f * rho * xy);
-  return 1.0f;
+}
+
+__device__ __forceinline__ float jinc_tab(const float4* __restrict__ tab, float z) {
+  const float s = z * (1.0f / kJincH);
+  if (s >= (float)kJincN) return jinc2(z);
+  const float fi = floorf(s);
+  const float t = s - fi;
+  const float4 c = tab[(int)fi];
+  return fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
 }
 
 template <int VB, int CT>
-__global__ __launch_bounds__(256) void k_render(RenderParams P) {
+__global__ __launch_bounds__(256) void k_render(RenderParams P, int nchunks) {
   __shared__ ViewRec s_v[VB];
-  const int v0 = blockIdx.y * VB;
+  __shared__ float4 s_jinc[kJincN];
+  __shared__ float s_nodes[kJincN + 3];
+  // consecutive (remapped) blocks share a bin range and sit on one XCD, so
+  // the layer values of the range are read from HBM once per XCD
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int bin_block = b / nchunks;
+  const int v0 = (b - bin_block * nchunks) * VB;
   const int nv = min(VB, P.V - v0);
   const ViewRec* views = reinterpret_cast<const ViewRec*>(P.views);
   if (threadIdx.x < VB && (int)threadIdx.x < nv) s_v[threadIdx.x] = views[v0 + threadIdx.x];
+  build_jinc_table(s_jinc, s_nodes);
   __syncthreads();
 
-  const int f = xcd_remap(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
+  const int f = bin_block * 256 + threadIdx.x;
   if (f >= P.F) return;
   double wxd, wyd;
   bin_freq(f, P.Wh, P.H, P.W, wxd, wyd);
   const float wx = (float)wxd, wy = (float)wyd;
+  const float wn = sqrtf(wx * wx + wy * wy);
   const int C = P.C;
   const size_t F = (size_t)P.F;
+
+  // per view: <u0, w>, focus, and the aperture scale of |s - d_k|:
+  // disk z = 2 pi rho |w| |s - d|, square arguments 2 rho w_x (s - d), 2 rho w_y (s - d)
+  float pv[VB], sv[VB], g1[VB], g2[VB];
+  int kind[VB];   // 0 pinhole, 1 disk, 2 square (uniform over the block)
+#pragma unroll
+  for (int v = 0; v < VB; ++v) {
+    const ViewRec rv = s_v[v < nv ? v : 0];
+    const int shape = __builtin_amdgcn_readfirstlane(rv.shape);
+    const bool open = __builtin_amdgcn_readfirstlane(__float_as_int(rv.radius)) != 0 &&
+                      __builtin_amdgcn_readfirstlane(__float_as_int(rv.radius)) != (int)0x80000000;
+    kind[v] = open && (shape == 1 || shape == 2) ? shape : 0;
+    pv[v] = rv.u * wx + rv.v * wy;
+    sv[v] = rv.focus;
+    g1[v] = rv.shape == 1 ? (float)kTwoPi * rv.radius * wn : 2.0f * rv.radius * wx;
+    g2[v] = 2.0f * rv.radius * wy;
+  }
 
   float2 acc[VB][CT];
 #pragma unroll
@@ -109,20 +150,38 @@ __global__ __launch_bounds__(256) void k_render(RenderParams P) {
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[v][c] = make_float2(0.f, 0.f);
 
+  // Layer k + 1 (and d_{k+1}) is loaded while layer k is processed.  Loads
+  // are unconditional (channel and layer indices clamped) so that the waits
+  // name only the oldest batch; channels c >= C repeat channel C - 1 and are
+  // never stored.  d travels as a vector load (lane-varying zero offset):
+  // a scalar load would share its wait counter with the LDS table reads.
+  int vzero;
+  asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
+  const float* dp = P.d + vzero;
+  const float2* lp = P.layer_spec + f;
+  float dn;
+  float2 xn[CT];
+  auto load_layer = [&](int k) {
+    dn = dp[k];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) xn[c] = lp[((size_t)k * C + (c < C ? c : C - 1)) * F];
+  };
+  load_layer(0);
   for (int k = 0; k < P.n; ++k) {
-    const float dk = P.d[k];
+    const float dk = dn;
     float2 x[CT];
 #pragma unroll
-    for (int c = 0; c < CT; ++c)
-      x[c] = c < C ? P.layer_spec[((size_t)k * C + c) * F + f] : make_float2(0.f, 0.f);
+    for (int c = 0; c < CT; ++c) x[c] = xn[c];
+    load_layer(min(k + 1, P.n - 1));
 #pragma unroll
     for (int v = 0; v < VB; ++v) {
       if (v < nv) {
-        const ViewRec rv = s_v[v];
         float s, co;
-        sincos2pi_f(dk * (rv.u * wx + rv.v * wy), s, co);
-        const float a = rv.focus - dk;
-        const float g = psi_hat_f(rv.shape, rv.radius, a * wx, a * wy);
+        sincos2pi_f(dk * pv[v], s, co);
+        const float a = sv[v] - dk;
+        float g = 1.0f;
+        if (kind[v] == 1) g = jinc_tab(s_jinc, g1[v] * fabsf(a));
+        else if (kind[v] == 2) g = sinc_fast(g1[v] * a) * sinc_fast(g2[v] * a);
         const float pr = co * g, pi = s * g;
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
@@ -144,8 +203,9 @@ __global__ __launch_bounds__(256) void k_render(RenderParams P) {
 
 template <int VB, int CT>
 static hipError_t launch_render_vc(const RenderParams& P, hipStream_t s) {
-  dim3 grid((P.F + 255) / 256, (P.V + VB - 1) / VB);
-  hipLaunchKernelGGL((k_render<VB, CT>), grid, dim3(256), 0, s, P);
+  const int nchunks = (P.V + VB - 1) / VB;
+  const int bin_blocks = (P.F + 255) / 256;
+  hipLaunchKernelGGL((k_render<VB, CT>), dim3(bin_blocks * nchunks), dim3(256), 0, s, P, nchunks);
   return hipGetLastError();
 }
 
