@@ -180,7 +180,7 @@ __device__ __forceinline__ void reg_fft(float2 (&a)[N]) {
 // so thread t (1) loads x[t + P q], q < Q, (2) transforms them in registers
 // (length Q), (3) multiplies by W_H^{t k1}, (4) passes the Q values through
 // LDS, (5) takes Q/P of the k1 rows and transforms each over t in registers
-// (length P), (6) stores X[k1 + Q k2].  Loads and stores of a wave cover whole
+// (length P), (6) stores X[k1 + Q k2].  Loads and stores of a wave cover
 // 128-byte row segments (16 columns x 8 bytes); the LDS tile uses padded
 // strides (k1 stride P + 1, column stride = 4 mod 32 entries) so that both
 // access patterns spread over the banks.
@@ -192,8 +192,11 @@ __global__ __launch_bounds__(TC * P) void k_fft_cols_reg(float2* __restrict__ da
   constexpr int CS0 = Q * KS;
   constexpr int CS = CS0 + ((36 - CS0 % 32) % 32);
   __shared__ float2 lds[TC * CS];
-  const int img = blockIdx.x / tiles;
-  const int c0 = (blockIdx.x - img * tiles) * TC;
+  // rows of W/2 + 1 complex values are not 128-byte aligned, so neighbouring
+  // tiles share cache lines: keep them on one XCD (one L2)
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int img = b / tiles;
+  const int c0 = (b - img * tiles) * TC;
   const int col = threadIdx.x % TC;
   const int t = threadIdx.x / TC;
   const bool live = c0 + col < Wh;
@@ -252,6 +255,160 @@ static bool cols_reg(float2* data, int batch, int H, int Wh, hipStream_t s, hipE
     case 512: err = go_cols_reg<16, 32, 16, INV>(data, batch, Wh, s); return true;
     case 768: err = go_cols_reg<16, 48, 8, INV>(data, batch, Wh, s); return true;
     case 1024: err = go_cols_reg<32, 32, 8, INV>(data, batch, Wh, s); return true;
+    default: return false;
+  }
+}
+
+// ---- rows, register four-step versions ---------------------------------------
+// Complex length N = W/2 = P Q (Q a multiple of P), P threads per row, 256/P
+// rows per block; same decomposition as the column kernel above.  Thread t
+// of a row reads z[t + P q] (P threads cover a contiguous P x 8-byte
+// segment).  The per-row LDS region holds Y[k1][t] (k1 stride P + 1) and
+// then, in the forward kernel, Z in natural order for the real split.
+template <int P, int Q>
+__global__ __launch_bounds__(256) void k_rfft_rows_reg(const float* __restrict__ img, float2* __restrict__ out,
+                                                       int nrows) {
+  constexpr int N = P * Q;
+  constexpr int RPB = 256 / P;
+  constexpr int KS = P + 1;
+  constexpr int RS = Q * KS;
+  __shared__ float2 lds[RPB * RS];
+  const int lr = threadIdx.x / P;
+  const int t = threadIdx.x - lr * P;
+  const int row = blockIdx.x * RPB + lr;
+  const bool live = row < nrows;
+  const float2* src = reinterpret_cast<const float2*>(img) + (size_t)row * N + t;
+  float2 v[Q];
+  static_for<0, Q>([&](auto QQ) {
+    constexpr int q = decltype(QQ)::value;
+    v[q] = live ? src[P * q] : make_float2(0.0f, 0.0f);
+  });
+  reg_fft<Q, false>(v);
+  const float step = -(float)t * (1.0f / (float)N);
+  static_for<1, Q>([&](auto KK) {
+    constexpr int k1 = decltype(KK)::value;
+    v[k1] = f2mul(v[k1], twiddle(step * (float)k1));
+  });
+  float2* mine = lds + lr * RS;
+  static_for<0, Q>([&](auto KK) {
+    constexpr int k1 = decltype(KK)::value;
+    mine[k1 * KS + t] = v[k1];
+  });
+  __syncthreads();
+  float2 w[Q / P][P];
+  static_for<0, Q / P>([&](auto SS) {
+    constexpr int s = decltype(SS)::value;
+    const int k1 = t + P * s;
+    static_for<0, P>([&](auto PP) {
+      constexpr int p = decltype(PP)::value;
+      w[s][p] = mine[k1 * KS + p];
+    });
+    reg_fft<P, false>(w[s]);
+  });
+  __syncthreads();
+  static_for<0, Q / P>([&](auto SS) {
+    constexpr int s = decltype(SS)::value;
+    static_for<0, P>([&](auto KK) {
+      constexpr int k2 = decltype(KK)::value;
+      mine[t + P * s + Q * k2] = w[s][k2];
+    });
+  });
+  __syncthreads();
+  if (!live) return;
+  // X[k] = E[k] + e^{-2 pi i k / W} O[k], k = 0..N
+  float2* dst = out + (size_t)row * (N + 1);
+  const float invW = 0.5f / (float)N;
+  for (int k = t; k <= N; k += P) {
+    const float2 zk = mine[k == N ? 0 : k];
+    const float2 zn = f2conj(mine[k == 0 ? 0 : N - k]);
+    const float2 E = f2scale(f2add(zk, zn), 0.5f);
+    const float2 O = f2scale(rot90<false>(f2sub(zk, zn)), 0.5f);
+    dst[k] = f2add(E, f2mul(twiddle(-(float)k * invW), O));
+  }
+}
+
+template <int P, int Q>
+__global__ __launch_bounds__(256) void k_irfft_rows_reg(const float2* __restrict__ spec, float* __restrict__ img,
+                                                        int nrows, float scale) {
+  constexpr int N = P * Q;
+  constexpr int RPB = 256 / P;
+  constexpr int KS = P + 1;
+  constexpr int RS = Q * KS;
+  __shared__ float2 lds[RPB * RS];
+  const int lr = threadIdx.x / P;
+  const int t = threadIdx.x - lr * P;
+  const int row = blockIdx.x * RPB + lr;
+  const bool live = row < nrows;
+  const float2* src = spec + (size_t)row * (N + 1);
+  // Z[k] = E[k] + i O[k], E = (X[k] + conj X[N-k]) / 2,
+  // O = e^{+2 pi i k / W} (X[k] - conj X[N-k]) / 2 (imaginary parts of X[0], X[N] dropped)
+  const float invW = 0.5f / (float)N;
+  float2 v[Q];
+  static_for<0, Q>([&](auto QQ) {
+    constexpr int q = decltype(QQ)::value;
+    const int k = t + P * q;
+    float2 xk = make_float2(0.0f, 0.0f), xn = make_float2(0.0f, 0.0f);
+    if (live) {
+      xk = src[k];
+      xn = src[N - k];
+    }
+    if (k == 0) { xk.y = 0.0f; xn.y = 0.0f; }
+    xn = f2conj(xn);
+    const float2 E = f2scale(f2add(xk, xn), 0.5f);
+    const float2 O = f2scale(f2mul(twiddle((float)k * invW), f2sub(xk, xn)), 0.5f);
+    v[q] = f2add(E, rot90<true>(O));
+  });
+  reg_fft<Q, true>(v);
+  const float step = (float)t * (1.0f / (float)N);
+  static_for<1, Q>([&](auto KK) {
+    constexpr int k1 = decltype(KK)::value;
+    v[k1] = f2mul(v[k1], twiddle(step * (float)k1));
+  });
+  float2* mine = lds + lr * RS;
+  static_for<0, Q>([&](auto KK) {
+    constexpr int k1 = decltype(KK)::value;
+    mine[k1 * KS + t] = v[k1];
+  });
+  __syncthreads();
+  if (!live) return;
+  float2* dst = reinterpret_cast<float2*>(img + (size_t)row * 2 * N);
+  static_for<0, Q / P>([&](auto SS) {
+    constexpr int s = decltype(SS)::value;
+    const int k1 = t + P * s;
+    float2 w[P];
+    static_for<0, P>([&](auto PP) {
+      constexpr int p = decltype(PP)::value;
+      w[p] = mine[k1 * KS + p];
+    });
+    reg_fft<P, true>(w);
+    static_for<0, P>([&](auto KK) {
+      constexpr int k2 = decltype(KK)::value;
+      dst[k1 + Q * k2] = f2scale(w[k2], scale);
+    });
+  });
+}
+
+template <int P, int Q>
+static hipError_t go_rows_reg(const FftParams& F, bool inverse, float scale, hipStream_t s) {
+  constexpr int RPB = 256 / P;
+  const int nrows = F.batch * F.H;
+  const dim3 grid((nrows + RPB - 1) / RPB);
+  if (inverse) hipLaunchKernelGGL((k_irfft_rows_reg<P, Q>), grid, dim3(256), 0, s, F.cplx, F.real, nrows, scale);
+  else hipLaunchKernelGGL((k_rfft_rows_reg<P, Q>), grid, dim3(256), 0, s, F.real, F.cplx, nrows);
+  return hipGetLastError();
+}
+
+// Register row kernels for the row lengths they are instantiated for; false
+// for the others (the LDS Stockham kernels below take them).
+static bool rows_reg(const FftParams& F, bool inverse, float scale, hipStream_t s, hipError_t& err) {
+  switch (F.W / 2) {
+    case 64: err = go_rows_reg<8, 8>(F, inverse, scale, s); return true;
+    case 128: err = go_rows_reg<8, 16>(F, inverse, scale, s); return true;
+    case 192: err = go_rows_reg<8, 24>(F, inverse, scale, s); return true;
+    case 256: err = go_rows_reg<16, 16>(F, inverse, scale, s); return true;
+    case 384: err = go_rows_reg<8, 48>(F, inverse, scale, s); return true;
+    case 512: err = go_rows_reg<16, 32>(F, inverse, scale, s); return true;
+    case 1024: err = go_rows_reg<32, 32>(F, inverse, scale, s); return true;
     default: return false;
   }
 }
@@ -383,13 +540,16 @@ hipError_t launch_rfft2(const FftParams& P, hipStream_t s) {
   const int N = P.W / 2;
   // rows
   {
-    const int G = pick_threads(N);
-    const int rpb = 256 / G;
-    const int nrows = P.batch * P.H;
-    const size_t lds = (size_t)rpb * 2 * N * sizeof(float2);
-    hipLaunchKernelGGL(k_rfft_rows, dim3((nrows + rpb - 1) / rpb), dim3(rpb * G), lds, s, P.real, P.cplx, nrows,
-                       P.W, P.row_plan, G);
-    hipError_t e = hipGetLastError();
+    hipError_t e = hipSuccess;
+    if (!rows_reg(P, false, 1.0f, s, e)) {
+      const int G = pick_threads(N);
+      const int rpb = 256 / G;
+      const int nrows = P.batch * P.H;
+      const size_t lds = (size_t)rpb * 2 * N * sizeof(float2);
+      hipLaunchKernelGGL(k_rfft_rows, dim3((nrows + rpb - 1) / rpb), dim3(rpb * G), lds, s, P.real, P.cplx, nrows,
+                         P.W, P.row_plan, G);
+      e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
   }
   // columns
@@ -426,11 +586,13 @@ hipError_t launch_irfft2(const FftParams& P, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   {
+    const float scale = 1.0f / ((float)P.H * (float)N);   // E, O above already carry the 1/2
+    hipError_t e = hipSuccess;
+    if (rows_reg(P, true, scale, s, e)) return e;
     const int G = pick_threads(N);
     const int rpb = 256 / G;
     const int nrows = P.batch * P.H;
     const size_t lds = (size_t)rpb * 2 * N * sizeof(float2);
-    const float scale = 1.0f / ((float)P.H * (float)N);   // E, O above already carry the 1/2
     hipLaunchKernelGGL(k_irfft_rows, dim3((nrows + rpb - 1) / rpb), dim3(rpb * G), lds, s, P.cplx, P.real, nrows,
                        P.W, P.row_plan, G, scale);
   }

@@ -15,7 +15,7 @@ def fdl():
 
 
 SIZES = [(1, 2), (3, 4), (8, 8), (12, 16), (24, 36), (128, 128), (256, 256), (384, 384), (512, 512),
-         (96, 512), (512, 96), (4096, 8), (2, 8192), (64, 64), (768, 24), (1024, 48), (512, 36)]
+         (96, 512), (512, 96), (4096, 8), (2, 8192), (64, 64), (768, 24), (1024, 48), (512, 36), (8, 768), (6, 1024), (2, 2048)]
 
 
 @pytest.mark.parametrize("H,W", SIZES)
