@@ -20,7 +20,12 @@ Also reported: rendered views/s, per-stage times, the roofline of the
 dominant kernel (construction, FP64 VALU-bound), and the FP64 CPU oracle
 timed on a bounded sample of the same construction.
 
-    python bench.py [--gpus 1] [--steps 10] [--warmup 3]
+Measured beside them on the same device: the achievable HBM bandwidth (a
+plain 1 GiB device copy) and FP64 VALU rate (fdl_fma64_probe), and, when the
+committed rocprofv3 counters match the kernel source, the construction
+kernel's executed-instruction issue fraction.
+
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5]
 """
 from __future__ import annotations
 
@@ -53,18 +58,51 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def load_traffic():
-    """HBM bytes per construct launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
+def load_counters():
+    """The committed rocprofv3 counter record of the construction kernel (HBM
+    bytes and VALU instructions per launch), or {} when the kernel source
+    changed since the counters were taken."""
     path = os.path.join(ROOT, "profiles", "construct_config2_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
-        return None
+        return {}
     if rec.get("kernel_source_hash") != kernel_source_hash():
-        return None
-    return rec.get("hbm_bytes_per_launch")
+        return {}
+    return rec
+
+
+def achievable(fdl, dev):
+    """Achievable HBM bandwidth (1 GiB device-to-device copy, bytes read +
+    written) and FP64 VALU rate (fdl_fma64_probe over 8 blocks per CU)."""
+    import torch
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) * 1e-3 / reps
+
+    src = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    t_copy = timed(lambda: dst.copy_(src))
+    hbm = 2 * src.numel() * 4 / t_copy / 1e9
+    del src, dst
+    out = torch.empty(256 * 8 * 256, dtype=torch.float64, device=dev)
+    flops = [0.0]
+
+    def fma():
+        flops[0] = fdl.fma64_probe(out, 4096)
+
+    t_fma = timed(fma)
+    return {"hbm_copy_GBs": hbm, "fp64_fma_TFLOPs": flops[0] / t_fma / 1e12}
 
 
 def cpu_baseline(u, d):
@@ -100,9 +138,20 @@ def cpu_baseline(u, d):
         with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
             list(ex.map(run, chunks))
         dt = time.perf_counter() - t0
+        one = idx[:4096]                 # single-thread mode on the first 4096 bins
+        t1 = time.perf_counter()
+        run(one)
+        dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": nbins / dt, "unit": "bins/s", "cores": workers, "kind": "oracle",
             "sample": f"FP64 oracle construct of {nbins} of the {F} bins (81 views, 30 layers, 3 channels), "
-                      f"{workers} threads, {dt:.1f} s"}
+                      f"{workers} threads, {dt:.1f} s; single thread on {one.size} bins, {dt1:.1f} s",
+            "single_thread_value": one.size / dt1, "host_cpus": os.cpu_count(), "cpu_model": model}
 
 
 def systems(fdl, synth, dev, serve_seconds: float):
@@ -187,8 +236,8 @@ def systems(fdl, synth, dev, serve_seconds: float):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-systems", action="store_true")
     ap.add_argument("--serve-seconds", type=float, default=3.0)
@@ -297,13 +346,23 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     stage_us = {s: float(np.mean([a.elapsed_time(b) for a, b in ev[s]]) * 1e3) for s in stages}
+    step_ms = [ev[stages[0]][i][0].elapsed_time(ev[stages[-1]][i][1]) for i in range(args.steps)]
 
     flops = construct_flops_per_bin(m, n, C) * F
     t_con = stage_us["construct"] * 1e-6
     achieved = flops / t_con / 1e12
+    cnt = load_counters()
+    ach = achievable(fdl, dev)
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": load_traffic(),
-            "kernel": "k_construct<2,3,true>", "flops_per_launch": flops}
+            "frac": achieved / PEAK_FP64_TFLOPS, "traffic": cnt.get("hbm_bytes_per_launch"),
+            "kernel": "k_construct<2,3,true>", "flops_per_launch": flops,
+            "achievable_peak": ach["fp64_fma_TFLOPs"], "frac_of_achievable": achieved / ach["fp64_fma_TFLOPs"]}
+    if cnt.get("valu_insts_per_launch"):
+        # time the counted VALU instructions need at one wave instruction per
+        # 4 cycles on each of the 1024 SIMDs at 2.4 GHz, over the measured time
+        t_issue = cnt["valu_insts_per_launch"] * 4.0 / (1024 * 2.4e9)
+        roof["executed_valu_insts"] = cnt["valu_insts_per_launch"]
+        roof["executed_issue_frac"] = t_issue / t_con
 
     sysres = None
     if not args.no_systems:
@@ -332,7 +391,9 @@ def main():
                                "calibration rows on 7x7 views 256x256, 16 layers, 4096 bins",
                    "bins": F, "views": m, "layers": n, "channels": C, "rendered_views": V},
         "rendered_views_per_s": V / (ms_per_step * 1e-3),
+        "median_step_ms": float(np.median(step_ms)),
         "stage_us": stage_us,
+        "achievable": ach,
         "roofline": roof,
         "cpu_baseline": base,
     }

@@ -258,6 +258,15 @@ int fdl_batch_plan_get_tuning(const fdl_batch_plan* plan, int32_t* mode, int32_t
 int fdl_batch_plan_set_tuning(fdl_batch_plan* plan, int32_t mode, int32_t chunk, int32_t grid_per_cu);
 int fdl_batch_plan_destroy(fdl_batch_plan* plan);
 
+/* ---------------------------------------------------------------------------
+ * Measurement utility (not part of the method): enqueues `blocks` blocks of
+ * 256 threads, each thread running 8 independent FP64 multiply-add chains of
+ * `iters` steps (16 * iters flops per thread) and writing one double to
+ * out_dev[blocks * 256].  Timed by the caller, it gives the achievable FP64
+ * VALU throughput against which the kernels above are compared.
+ * FDL_EINVAL for a null pointer or non-positive sizes. */
+int fdl_fma64_probe(double* out_dev, int blocks, int iters, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -87,6 +87,8 @@ def lib():
         L.fdl_batch_plan_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.fdl_batch_plan_set_tuning.restype = i32
         L.fdl_batch_plan_set_tuning.argtypes = [vp, i32, i32, i32]
+    L.fdl_fma64_probe.restype = i32
+    L.fdl_fma64_probe.argtypes = [vp, i32, i32, vp]
     _lib = L
     return L
 
@@ -236,6 +238,17 @@ def gd_step(u: torch.Tensor, d: torch.Tensor, grad_u: torch.Tensor, grad_d: torc
     _check(grad_d, torch.float64, (n,), "grad_d")
     _call("fdl_gd_step", u.data_ptr(), d.data_ptr(), grad_u.data_ptr(), grad_d.data_ptr(), m, n,
           float(alpha), float(eps_g), _stream(u))
+
+
+def fma64_probe(out: torch.Tensor, iters: int) -> float:
+    """Enqueue the FP64 multiply-add loop (fdl_fma64_probe) over out.numel()/256
+    blocks; returns the flops it performs (16 per thread per iteration)."""
+    _check(out, torch.float64, None, "out")
+    if out.numel() % 256:
+        raise ValueError("out must hold a multiple of 256 doubles")
+    blocks = out.numel() // 256
+    _call("fdl_fma64_probe", out.data_ptr(), blocks, int(iters), _stream(out))
+    return 16.0 * out.numel() * iters
 
 
 class LFDesc(ctypes.Structure):

@@ -50,3 +50,4 @@ def test_host_side_validation_without_gpu():
     assert L.fdl_calib_grad(fake, fake, fake, 300, 4, 1, 8, 8, 0.01, 0.001, 1, 1, None, 0,
                             fake, fake, fake, fake, 1 << 20, None) == -2
     assert L.fdl_calib_workspace(49, 16, 4096) == 2048 * (1 + 98 + 16) * 8
+    assert L.fdl_fma64_probe(None, 1, 1, None) == -1
