@@ -209,6 +209,44 @@ def systems(fdl, synth, dev, serve_seconds: float):
     del items
     torch.cuda.empty_cache()
 
+    # calibration loop (7x7 / 256^2 / 16 layers, LOO loss, 4096 bins per step):
+    # 200 steps issued eagerly vs the same steps captured once in a HIP graph
+    c5, u5_0, d5_0 = synth.config5()
+    l5 = fdl.rfft2(torch.from_numpy(c5.layers).to(dev))
+    p5 = torch.zeros((c5.m, 5), dtype=torch.float32)
+    p5[:, 0:2] = torch.from_numpy(c5.u)
+    v5 = fdl.irfft2(fdl.render(l5, torch.from_numpy(c5.d).to(dev), fdl.view_records(p5.to(dev)), c5.H, c5.W),
+                    c5.H, c5.W) + torch.from_numpy(c5.noise).to(dev)
+    b5 = fdl.rfft2(v5)
+    F5 = c5.H * (c5.W // 2 + 1)
+    nsteps = 200
+    rng = np.random.default_rng(5)
+    subs = torch.from_numpy(np.stack([synth.frequency_subset(F5, 4096, rng) for _ in range(nsteps)])).to(dev)
+    u5 = torch.from_numpy(u5_0).to(dev)
+    d5 = torch.from_numpy(d5_0).to(dev)
+    g5 = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((c5.m, 2), dtype=torch.float64, device=dev),
+          torch.empty(c5.n, dtype=torch.float64, device=dev))
+    ws = torch.empty(fdl.calib_workspace_bytes(c5.m, c5.n, 4096), dtype=torch.uint8, device=dev)
+
+    def loop():
+        for i in range(nsteps):
+            fdl.calib_grad(b5, u5, d5, c5.H, c5.W, c5.lam, c5.eps, c5.reg, fdl.LOSS_LOO, subs[i], out=g5, ws=ws)
+            fdl.gd_step(u5, d5, g5[1], g5[2], 0.2, 1e-6)
+
+    t_eager = timed(loop, reps=2)
+    gr5 = torch.cuda.CUDAGraph()
+    st5 = torch.cuda.Stream(device=dev)
+    st5.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(st5):
+        with torch.cuda.graph(gr5, stream=st5):
+            loop()
+    torch.cuda.current_stream(dev).wait_stream(st5)
+    t_graph5 = timed(gr5.replay, reps=2)
+    out["calibration"] = {"steps": nsteps, "eager_steps_per_s": nsteps / (t_eager * 1e-3),
+                          "graph_steps_per_s": nsteps / (t_graph5 * 1e-3), "graph_speedup": t_eager / t_graph5}
+    del gr5, b5, subs, ws
+    torch.cuda.empty_cache()
+
     if serve_seconds > 0:
         from paper_1901_06919_amd.serve import FDLServer, PoolEntry
         c2 = synth.config2(H=8, W=8)          # positions / disparities only
@@ -406,6 +444,8 @@ def main():
             out["p99_request_ms"] = sv["continuous"].get("all_p99_ms")
         if sysres.get("serving_1000rps"):
             out["serving_1000rps"] = sysres["serving_1000rps"]
+        if sysres.get("calibration"):
+            out["calibration"] = sysres["calibration"]
     print(json.dumps(out))
 
 

@@ -230,6 +230,51 @@ def render_images(layer_spec: np.ndarray, d: np.ndarray, views: np.ndarray, H: i
     return irfft2(render(layer_spec, d, views, H, W), H, W)
 
 
+def a_matrix_views(views: np.ndarray, d: np.ndarray, wx: np.ndarray, wy: np.ndarray) -> np.ndarray:
+    """Eq. AMatGeneral with an aperture per input view:
+    A_jk(w) = exp(+2 pi i d_k <u_j, w>) psi_hat_j((s_j - d_k) w), views [m, 5]
+    rows (u, v, focus s, radius rho, shape) as for :func:`render` (the input
+    view j is the rendering of the layers with its own aperture and focus).
+    wx, wy are the bins' frequencies ([F]); returns [F, m, n] complex128."""
+    views = np.asarray(views, dtype=np.float64).reshape(-1, 5)
+    d = np.asarray(d, dtype=np.float64)
+    A = a_matrix(views[:, 0:2], d, wx, wy)
+    for j, (_, _, s, rho, shape) in enumerate(views):
+        for k in range(d.shape[0]):
+            A[:, j, k] *= psi_hat(int(round(shape)), rho, (s - d[k]) * wx, (s - d[k]) * wy)
+    return A
+
+
+def construct_views(view_spec: np.ndarray, views: np.ndarray, d: np.ndarray, H: int, W: int,
+                    lam: float, eps: float, reg: int = REG_VIEW2,
+                    freq_index: Optional[np.ndarray] = None, chunk: int = 2048) -> np.ndarray:
+    """Layer construction from input views taken with their own apertures
+    (focal stacks, wide-aperture or mixed inputs; Eq. AMatGeneral, Sec. V-A):
+    the closed form of :func:`construct` with A from :func:`a_matrix_views`.
+    Returns layer spectra [n, C, H, W//2+1] complex128, or [n, C, len(freq_index)]."""
+    view_spec = np.asarray(view_spec)
+    m, C = view_spec.shape[:2]
+    n = len(d)
+    wx_all, wy_all = flat_freqs(H, W)
+    b_all = view_spec.reshape(m, C, -1)
+    if freq_index is None:
+        freq_index = np.arange(wx_all.shape[0])
+    freq_index = np.asarray(freq_index, dtype=np.int64)
+    out = np.zeros((n, C, freq_index.shape[0]), dtype=np.complex128)
+    for s in range(0, freq_index.shape[0], chunk):
+        fi = freq_index[s:s + chunk]
+        wx, wy = wx_all[fi], wy_all[fi]
+        A = a_matrix_views(views, d, wx, wy)
+        M = normal_matrix(A, reg_matrix(reg, d, wx, wy), lam, eps)
+        b = np.transpose(b_all[:, :, fi], (2, 0, 1)).astype(np.complex128)
+        c = np.conj(np.swapaxes(A, -1, -2)) @ b
+        x = np.linalg.solve(M, c)
+        out[:, :, s:s + chunk] = np.transpose(x, (1, 2, 0))
+    if freq_index.shape[0] == wx_all.shape[0] and np.array_equal(freq_index, np.arange(wx_all.shape[0])):
+        return out.reshape(n, C, H, W // 2 + 1)
+    return out
+
+
 def forward_views(layers: np.ndarray, u: np.ndarray, d: np.ndarray) -> np.ndarray:
     """Sub-aperture views of a layer stack (Eq. FourierView): the spectra of
     the spatial layers [n, C, H, W] phase-shifted to each position u_j and
