@@ -163,6 +163,24 @@ int fdl_render(const fdl_c64* layer_spec_dev, const float* d_dev, int n, int C, 
                const fdl_view* views_dev, int V, fdl_c64* out_spec_dev, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Layer construction from input views that carry their own apertures
+ * (Eq. AMatGeneral: focal stacks, wide-aperture or mixed inputs, Sec. V-A):
+ *   A_jk = exp(2 pi i d_k <u_j, w>) psi_hat_j((s_j - d_k) w),
+ * psi_hat_j the unit-integral aperture spectrum of input view j, as in
+ * fdl_render (disk of radius rho: 2 J1(z)/z, z = 2 pi rho |xi|; square of
+ * half-side rho: sinc(2 rho xi_x) sinc(2 rho xi_y); pinhole or rho = 0: 1),
+ * s_j its focus; then M and x exactly as fdl_construct.  The aperture spectra
+ * are evaluated in FP64 (power series / Hankel expansion of J1, about 1e-13).
+ *   views_dev [m] fdl_view on the device: (u, v) position, focus s, radius,
+ *   shape of each INPUT view (the same record as a rendered view);
+ *   all other arguments, layouts and errors as fdl_construct.
+ * The Toeplitz form of A^H A does not apply (|A_jk| varies), so the cost per
+ * bin grows as m n^2 instead of m n. */
+int fdl_construct_views(const fdl_c64* view_spec_dev, const fdl_view* views_dev, const float* d_host, int m, int n,
+                        int C, int H, int W, float lambda, float eps, int reg, fdl_c64* layer_spec_dev,
+                        int32_t* status_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Calibration loss and gradient (Sec. V-B).  Over the Q bins freq_idx_dev
  * (flat half-spectrum indices, or all F = H(W/2+1) bins when freq_idx_dev is
  * NULL), with orthonormal spectra b = view_spec / sqrt(H W):

@@ -54,6 +54,8 @@ def lib():
     L.fdl_version.argtypes = []
     L.fdl_construct.restype = i32
     L.fdl_construct.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, vp, vp, vp]
+    L.fdl_construct_views.restype = i32
+    L.fdl_construct_views.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, vp, vp, vp]
     L.fdl_render.restype = i32
     L.fdl_render.argtypes = [vp, vp, i32, i32, i32, i32, vp, i32, vp, vp]
     for name in ("fdl_rfft2", "fdl_irfft2"):
@@ -170,6 +172,36 @@ def construct(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int,
         _check(status, torch.int32, (1,), "status")
         sp = status.data_ptr()
     _call("fdl_construct", view_spec.data_ptr(), u.data_ptr(), d_host.data_ptr(), m, n, C, H, W,
+          float(lam), float(eps), int(reg), out.data_ptr(), sp, _stream(view_spec))
+    return out
+
+
+def construct_views(view_spec: torch.Tensor, views: torch.Tensor, d: torch.Tensor, H: int, W: int,
+                    lam: float, eps: float, reg: int = REG_VIEW2, out: Optional[torch.Tensor] = None,
+                    status: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Layer spectra [n, C, H, W//2+1] from view spectra [m, C, H, W//2+1] of
+    input views with their own apertures (fdl_construct_views).  ``views``
+    are [m, 5] float rows (u, v, focus, radius, shape) or records from
+    :func:`view_records`, one per input view."""
+    m, C = view_spec.shape[:2]
+    n = d.shape[0]
+    _check(view_spec, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
+    if not views.is_cuda:
+        raise ValueError("views must be a device tensor")
+    rec = views if getattr(views, "_fdl_records", False) else view_records(views)
+    if rec.shape[0] != m:
+        raise ValueError(f"views must describe the {m} input views, got {rec.shape[0]}")
+    if d.dtype != torch.float32 or d.dim() != 1:
+        raise TypeError("d must be a 1-D float32 tensor")
+    d_host = d.detach().to("cpu").contiguous()          # disparities travel by value
+    if out is None:
+        out = torch.empty((n, C, H, W // 2 + 1), dtype=torch.complex64, device=view_spec.device)
+    _check(out, torch.complex64, (n, C, H, W // 2 + 1), "out")
+    sp = 0
+    if status is not None:
+        _check(status, torch.int32, (1,), "status")
+        sp = status.data_ptr()
+    _call("fdl_construct_views", view_spec.data_ptr(), rec.data_ptr(), d_host.data_ptr(), m, n, C, H, W,
           float(lam), float(eps), int(reg), out.data_ptr(), sp, _stream(view_spec))
     return out
 

@@ -231,6 +231,7 @@ int fdl_batch_plan_create(const fdl_lf_desc* descs_host, int B, int mode, fdl_ba
     fdl::ConstructParams& P = p->host_params[i];
     P.view_spec = reinterpret_cast<const float2*>(D.view_spec);
     P.u = reinterpret_cast<const float2*>(D.u);
+    P.views = nullptr;
     P.layer_spec = reinterpret_cast<float2*>(D.layer_spec);
     P.status = D.status;
     P.m = D.m; P.n = D.n; P.C = D.C; P.H = D.H; P.W = D.W; P.Wh = D.W / 2 + 1; P.F = D.H * (D.W / 2 + 1);

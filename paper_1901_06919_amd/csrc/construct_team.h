@@ -41,6 +41,72 @@ __device__ __forceinline__ void team_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// ---- aperture spectra in FP64 (inputs with their own apertures) -------------
+// 2 J1(z)/z: its power series sum_k (-1)^k (z/2)^(2k) / (k! (k+1)!) through
+// k = 26 for z <= 12 (largest term about 700, so about 1e-13 absolute), and
+// for z > 12 the Hankel expansion J1(z) = sqrt(2/(pi z)) (P cos chi - Q sin chi),
+// chi = z - 3 pi/4, with P = sum_k (-1)^k a_2k z^-2k, Q = sum_k (-1)^k a_2k+1
+// z^-(2k+1), a_k = prod_{i<=k} (4 - (2i-1)^2) / (k! 8^k), through k = 12
+// (truncation below 1e-13 at z = 12 and falling fast beyond).
+struct JincCoef {
+  double s[27], p[13], q[13];
+};
+constexpr JincCoef make_jinc_coef() {
+  JincCoef c{};
+  double f = 1.0;   // k! (k+1)!
+  for (int k = 0; k <= 26; ++k) {
+    if (k > 0) f *= (double)k * (double)(k + 1);
+    c.s[k] = (k % 2 ? -1.0 : 1.0) / f;
+  }
+  double a[26] = {};
+  a[0] = 1.0;
+  for (int k = 1; k < 26; ++k) a[k] = a[k - 1] * (4.0 - (double)((2 * k - 1) * (2 * k - 1))) / (8.0 * k);
+  for (int k = 0; k <= 12; ++k) {
+    c.p[k] = (k % 2 ? -1.0 : 1.0) * a[2 * k];
+    c.q[k] = (k % 2 ? -1.0 : 1.0) * a[2 * k + 1];
+  }
+  return c;
+}
+
+__device__ __forceinline__ double jinc64(double z) {
+  constexpr JincCoef K = make_jinc_coef();
+  if (z <= 12.0) {
+    const double y = 0.25 * z * z;
+    double s = K.s[26];
+    static_for<0, 26>([&](auto II) { s = fma(s, y, K.s[25 - decltype(II)::value]); });
+    return s;
+  }
+  const double iz = 1.0 / z, iz2 = iz * iz;
+  double p = K.p[12], q = K.q[12];
+  static_for<0, 12>([&](auto II) {
+    p = fma(p, iz2, K.p[11 - decltype(II)::value]);
+    q = fma(q, iz2, K.q[11 - decltype(II)::value]);
+  });
+  q *= iz;
+  double sn, cs;
+  sincos2pi(z * (1.0 / kTwoPi) - 0.375, sn, cs);   // chi in turns
+  const double j1 = sqrt(2.0 / (kPi * z)) * (p * cs - q * sn);
+  return 2.0 * j1 * iz;
+}
+
+// sin(pi t) / (pi t)
+__device__ __forceinline__ double sinc64(double t) {
+  const double a = kPi * t;
+  if (fabs(t) < 1e-6) return 1.0 - a * a * (1.0 / 6.0);
+  double sn, cs;
+  sincos2pi(0.5 * t, sn, cs);
+  return sn / a;
+}
+
+// psi_hat((s - d) w) of a unit-integral aperture (shape uniform over the
+// wave): disk of radius rho 2 J1(z)/z, z = 2 pi rho |s - d| |w|; square of
+// half-side rho sinc(2 rho (s - d) w_x) sinc(2 rho (s - d) w_y); else 1.
+__device__ __forceinline__ double aperture64(int shape, double rho, double a, double wx, double wy, double wn) {
+  if (shape == 1) return jinc64(kTwoPi * rho * fabs(a) * wn);
+  if (shape == 2) return sinc64(2.0 * rho * a * wx) * sinc64(2.0 * rho * a * wy);
+  return 1.0;
+}
+
 // Per-block table of exp(2 pi i t / kPhaseTab), t = 0..kPhaseTab-1.
 constexpr int kPhaseTab = 256;
 
@@ -152,9 +218,12 @@ __device__ __forceinline__ void team_transpose(TeamRows<R>& S, double2* tr, int 
   team_sync();
 }
 
-template <int R, int CT, bool TOEP>
+// APER: the inputs carry their own apertures (Eq. AMatGeneral):
+// A_jk = exp(2 pi i d_k p_j) psi_hat_j((s_j - d_k) w), general Gram path only.
+template <int R, int CT, bool TOEP, bool APER = false>
 __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>& T, const double2* __restrict__ tab,
                                            int f, int lane) {
+  static_assert(!(TOEP && APER), "apertures break the Toeplitz structure");
   // The system is padded to NMAX = 16 R unknowns with an identity block
   // (rows and columns >= n), so that every unrolled step below runs without
   // a branch on n: the padded unknowns have zero right-hand sides and solve
@@ -187,17 +256,33 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   const float2* bp = P.view_spec + f;
   const size_t F = (size_t)P.F;
   const int m = P.m;
-  // u is read through a lane-varying (zero) offset so that it travels as a
-  // vector load: a scalar load would share its wait counter with the LDS
-  // table reads and stall every one of them.
+  // Positions (and, with APER, focus, radius and shape) are read through a
+  // lane-varying (zero) offset so that they travel as vector loads: a scalar
+  // load would share its wait counter with the LDS table reads and stall
+  // every one of them.
   int vzero;
   asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
   const float2* up = P.u + vzero;
-  auto load = [&](int j, float2& u, float2 (&b)[CT]) {
-    u = up[j];
+  const float* vp = P.views + vzero;
+  struct ViewIn {
+    float2 u;
+    float s, rho;
+    int shape;
+  };
+  auto load = [&](int j, ViewIn& v, float2 (&b)[CT]) {
+    if constexpr (APER) {
+      const float* q = vp + 5 * (size_t)j;
+      v.u = make_float2(q[0], q[1]);
+      v.s = q[2];
+      v.rho = q[3];
+      v.shape = __float_as_int(q[4]);
+    } else {
+      v.u = up[j];
+    }
 #pragma unroll
     for (int c = 0; c < CT; ++c) b[c] = bp[((size_t)j * C + (c < C ? c : C - 1)) * F];
   };
+  const double wn = sqrt(wx * wx + wy * wy);
   cd m0[R], m1[R], m2[R], m3[R];
   if constexpr (TOEP) {
 #pragma unroll
@@ -209,11 +294,24 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
       for (int k = 0; k < 16 * (r + 1); ++k) S.template at<r>(k) = cd{0.0, 0.0};
     });
   }
-  auto view = [&](const float2 uj, const float2 (&bc)[CT]) {
-    const double p = fma((double)uj.x, wx, (double)uj.y * wy);
+  auto view = [&](const ViewIn& vj, const float2 (&bc)[CT]) {
+    const double p = fma((double)vj.u.x, wx, (double)vj.u.y * wy);
     cd A[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) A[r] = expi_tab(tab, dt[r], p);
+    if constexpr (APER) {
+      // the aperture of view j is the same in every lane of the wave
+      const int shape = __builtin_amdgcn_readfirstlane(vj.shape);
+      const float rho = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(vj.rho)));
+      if (rho != 0.0f && (shape == 1 || shape == 2)) {
+        sched_fence();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          A[r] = cscale(A[r], aperture64(shape, (double)rho, (double)vj.s - dk[r], wx, wy, wn));
+          sched_fence();
+        }
+      }
+    }
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
       const cd b = cd{(double)bc[c].x, (double)bc[c].y};
@@ -244,12 +342,25 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
       });
     }
   };
-  {
+  if constexpr (APER) {
+    // one view in flight: the aperture spectra already hold many registers
+    ViewIn ua;
+    float2 ba[CT];
+    load(0, ua, ba);
+    for (int j = 0; j < m; ++j) {
+      const ViewIn uj = ua;
+      float2 bj[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) bj[c] = ba[c];
+      load(min(j + 1, m - 1), ua, ba);
+      view(uj, bj);
+    }
+  } else {
     // three view buffers in rotation: the loads of a view are issued two
     // views before it is processed.  The prefetch index is clamped instead of
     // guarded, so that every load is unconditional and each wait can name the
     // oldest batch only (a guarded load forces waits for all loads in flight).
-    float2 ua, ub, uc;
+    ViewIn ua, ub, uc;
     float2 ba[CT], bb[CT], bc[CT];
     const int last = m - 1;
     load(0, ua, ba);

@@ -10,7 +10,8 @@ namespace fdl {
 // value (n <= 32), together with the host's classification of them.
 struct ConstructParams {
   const float2* view_spec;   // [m][C][F]
-  const float2* u;           // [m]
+  const float2* u;           // [m] positions (sub-aperture inputs)
+  const float* views;        // [m][5] fdl_view records (inputs with apertures) or null
   float2* layer_spec;        // [n][C][F]
   int* status;               // device counter or null
   int m, n, C, H, W, Wh, F;
@@ -31,6 +32,7 @@ struct RenderParams {
 
 hipError_t launch_construct_r1(const ConstructParams& P, hipStream_t s);   // n <= 16
 hipError_t launch_construct_r2(const ConstructParams& P, hipStream_t s);   // n <= 32
+hipError_t launch_construct_views(const ConstructParams& P, hipStream_t s);   // inputs with apertures
 hipError_t launch_render(const RenderParams& P, hipStream_t s);
 
 // Mixed-radix (4, 2, 3) plan for one FFT length.

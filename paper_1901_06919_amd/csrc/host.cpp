@@ -107,6 +107,7 @@ int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float
   fdl::ConstructParams P;
   P.view_spec = reinterpret_cast<const float2*>(view_spec_dev);
   P.u = reinterpret_cast<const float2*>(u_dev);
+  P.views = nullptr;
   P.layer_spec = reinterpret_cast<float2*>(layer_spec_dev);
   P.status = status_dev;
   P.m = m; P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F;
@@ -115,6 +116,32 @@ int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float
   trace("construct m n C F", m, n, C, (int)F);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   return map_hip(n <= 16 ? fdl::launch_construct_r1(P, s) : fdl::launch_construct_r2(P, s));
+}
+
+int fdl_construct_views(const fdl_c64* view_spec_dev, const fdl_view* views_dev, const float* d_host, int m, int n,
+                        int C, int H, int W, float lambda, float eps, int reg, fdl_c64* layer_spec_dev,
+                        int32_t* status_dev, void* stream) {
+  if (!view_spec_dev || !views_dev || !d_host || !layer_spec_dev) return FDL_EINVAL;
+  if (!(std::isfinite(lambda) && lambda >= 0.f) || !(std::isfinite(eps) && eps >= 0.f)) return FDL_EINVAL;
+  if (reg < FDL_REG_VIEW2 || reg > FDL_REG_L2) return FDL_EINVAL;
+  if (m < 1 || m > 4096 || n < 1 || n > FDL_MAX_LAYERS || C < 1 || C > FDL_MAX_CHANNELS) return FDL_ESHAPE;
+  if (H < 1 || W < 2 || (W & 1)) return FDL_ESHAPE;
+  for (int k = 0; k < n; ++k)
+    if (!std::isfinite(d_host[k])) return FDL_EINVAL;
+  const long long F = (long long)H * (W / 2 + 1);
+  if (F > (1LL << 30)) return FDL_ESHAPE;
+  fdl::ConstructParams P;
+  P.view_spec = reinterpret_cast<const float2*>(view_spec_dev);
+  P.u = nullptr;
+  P.views = reinterpret_cast<const float*>(views_dev);
+  P.layer_spec = reinterpret_cast<float2*>(layer_spec_dev);
+  P.status = status_dev;
+  P.m = m; P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F;
+  P.lambda = (double)lambda; P.eps = (double)eps; P.reg = reg;
+  fdl_host::classify(d_host, n, P);
+  P.toeplitz = 0;   // the apertures scale each A_jk: no Toeplitz Gram
+  trace("construct_views m n C F", m, n, C, (int)F);
+  return map_hip(fdl::launch_construct_views(P, reinterpret_cast<hipStream_t>(stream)));
 }
 
 int fdl_render(const fdl_c64* layer_spec_dev, const float* d_dev, int n, int C, int H, int W,

@@ -51,3 +51,5 @@ def test_host_side_validation_without_gpu():
                             fake, fake, fake, fake, 1 << 20, None) == -2
     assert L.fdl_calib_workspace(49, 16, 4096) == 2048 * (1 + 98 + 16) * 8
     assert L.fdl_fma64_probe(None, 1, 1, None) == -1
+    assert L.fdl_construct_views(None, fake, d, 4, 4, 1, 8, 8, 0.01, 0.001, 0, fake, None, None) == -1
+    assert L.fdl_construct_views(fake, fake, d, 4, 40, 1, 8, 8, 0.01, 0.001, 0, fake, None, None) == -2
