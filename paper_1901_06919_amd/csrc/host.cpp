@@ -150,8 +150,8 @@ int fdl_render(const fdl_c64* layer_spec_dev, const float* d_dev, int n, int C, 
   if (n < 1 || n > FDL_MAX_LAYERS || C < 1 || C > FDL_MAX_CHANNELS || V < 1) return FDL_ESHAPE;
   if (H < 1 || W < 2 || (W & 1)) return FDL_ESHAPE;
   const long long F = (long long)H * (W / 2 + 1);
-  // one block per (256 bins, chunk of at least 8 views)
-  if (F > (1LL << 30) || (F + 255) / 256 * ((V + 7) / 8) > 0x7fffffffLL) return FDL_ESHAPE;
+  // one block per (256 bins, chunk of at least 4 views)
+  if (F > (1LL << 30) || (F + 255) / 256 * ((V + 3) / 4) > 0x7fffffffLL) return FDL_ESHAPE;
   fdl::RenderParams P;
   P.layer_spec = reinterpret_cast<const float2*>(layer_spec_dev);
   P.d = d_dev;

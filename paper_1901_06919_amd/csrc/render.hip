@@ -209,12 +209,15 @@ static hipError_t launch_render_vc(const RenderParams& P, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Views per chunk: small chunks keep the accumulators few enough for high
+// occupancy, and the layer values re-read by the chunks of one bin range come
+// from the L2 of its XCD (sizes from a sweep on the 81-view 512^2 render).
 hipError_t launch_render(const RenderParams& P, hipStream_t s) {
   switch (P.C) {
-    case 1: return launch_render_vc<32, 1>(P, s);
-    case 2: return launch_render_vc<16, 2>(P, s);
-    case 3: return launch_render_vc<16, 3>(P, s);
-    default: return launch_render_vc<8, 4>(P, s);
+    case 1: return launch_render_vc<8, 1>(P, s);
+    case 2: return launch_render_vc<6, 2>(P, s);
+    case 3: return launch_render_vc<4, 3>(P, s);
+    default: return launch_render_vc<4, 4>(P, s);
   }
 }
 
