@@ -28,7 +28,7 @@
 namespace fdl {
 
 struct CalibLayout {   // offsets (in doubles) into the dynamic LDS of one block
-  int A, L, b, x, r, p, T, P, w, y, v, gam, Wm, red;
+  int A, L, inv, b, x, r, p, T, P, w, y, v, gam, Wm, red;
   int total;
 };
 
@@ -37,6 +37,7 @@ __host__ __device__ inline CalibLayout calib_layout(int m, int n, int C, int mod
   int at = 0;
   o.A = at; at += 2 * m * n;
   o.L = at; at += 2 * n * n;
+  o.inv = at; at += n;
   o.b = at; at += 2 * m * C;
   o.x = at; at += 2 * n * C;
   o.r = at; at += 2 * m * C;
@@ -77,7 +78,11 @@ __device__ __forceinline__ double reg_entry(int reg, int i, int k, int n, double
   return (i == k) ? lambda : 0.0;
 }
 
-__global__ __launch_bounds__(256) void k_calib(CalibParams P) {
+// At least 2 blocks per CU; the kernel compiles to about 160 VGPRs, which
+// leaves room for 3 (as many as the leave-one-out LDS of 49 views and 16
+// layers allows).  Asking for 3 forces a tighter allocation that measured
+// slower; inner loops are unrolled by 4 (8 measured slower too).
+__global__ __launch_bounds__(256, 2) void k_calib(CalibParams P) {
   constexpr int NT = 256;
   extern __shared__ double sm[];
   const int m = P.m, n = P.n, C = P.C;
@@ -96,20 +101,35 @@ __global__ __launch_bounds__(256) void k_calib(CalibParams P) {
   double gd = 0.0;              // layer k = t
   double loss = 0.0;
 
+  // The positions are the same for every bin: thread j keeps u_j.  The
+  // spectra of the next bin (m C <= 1024 values, at most 4 per thread) are
+  // loaded while the current bin is processed.
+  const float2 uj = t < m ? P.u[t] : make_float2(0.0f, 0.0f);
+  float2 bnext[4];
+  auto fetch = [&](int q) {
+    if (q >= P.Q) return;
+    const int fq = P.freq_idx ? P.freq_idx[q] : q;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = t + s * NT;
+      if (i < m * C) bnext[s] = P.view_spec[(size_t)i * F + fq];
+    }
+  };
+  fetch(blockIdx.x);
+
   for (int q = blockIdx.x; q < P.Q; q += gridDim.x) {
     const int f = P.freq_idx ? P.freq_idx[q] : q;
     double wx, wy;
     bin_freq(f, P.Wh, P.H, P.W, wx, wy);
     const double w2 = wx * wx + wy * wy, w4 = w2 * w2;
 
-    for (int j = t; j < m; j += NT) {
-      const float2 uj = P.u[j];
-      pj[j] = (double)uj.x * wx + (double)uj.y * wy;
+    if (t < m) pj[t] = (double)uj.x * wx + (double)uj.y * wy;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int i = t + s * NT;
+      if (i < m * C) stc(b, i, cd{(double)bnext[s].x * P.bscale, (double)bnext[s].y * P.bscale});
     }
-    for (int i = t; i < m * C; i += NT) {
-      const float2 v = P.view_spec[(size_t)i * F + f];
-      stc(b, i, cd{(double)v.x * P.bscale, (double)v.y * P.bscale});
-    }
+    fetch(q + gridDim.x);
     __syncthreads();
     for (int i = t; i < m * n; i += NT) {
       const int j = i / n, k = i - j * n;
@@ -121,6 +141,7 @@ __global__ __launch_bounds__(256) void k_calib(CalibParams P) {
       const int k1 = i / n, k2 = i - k1 * n;
       if (k2 > k1) continue;
       cd s = cd{0.0, 0.0};
+      #pragma unroll 4
       for (int j = 0; j < m; ++j) cfma_conj(s, ldc(A, j * n + k1), ldc(A, j * n + k2));
       s.re += reg_entry(P.reg, k1, k2, n, P.lambda, w4, (double)P.d[k1]) + (k1 == k2 ? P.eps : 0.0);
       if (k1 == k2) s.im = 0.0;
@@ -129,47 +150,78 @@ __global__ __launch_bounds__(256) void k_calib(CalibParams P) {
     for (int i = t; i < n * C; i += NT) {
       const int k = i / C, c = i - k * C;
       cd s = cd{0.0, 0.0};
+      #pragma unroll 4
       for (int j = 0; j < m; ++j) cfma_conj(s, ldc(A, j * n + k), ldc(b, j * C + c));
       stc(x, i, s);
     }
     __syncthreads();
-    // Cholesky (right-looking) in LDS; diagonal stored as L_jj
+    // Cholesky (right-looking) in LDS, one barrier per column: step j updates
+    // the trailing matrix with the unscaled column j (L_ik -= L_ij conj(L_kj) /
+    // piv_j) and scales column j-1, which no thread reads any more.  Only
+    // inv[j] = 1 / L_jj is kept: the diagonal itself is read by every thread
+    // as the pivot and is never overwritten (nothing later reads it).
+    double* inv = sm + o.inv;
     for (int j = 0; j < n; ++j) {
       double piv = L[2 * (j * n + j)];
       if (!(piv > 0.0)) piv = 1e-300;
-      const double inv = 1.0 / sqrt(piv);
-      __syncthreads();
-      for (int i = j + 1 + t; i < n; i += NT) stc(L, i * n + j, cscale(ldc(L, i * n + j), inv));
-      if (t == 0) { L[2 * (j * n + j)] = piv * inv; L[2 * (j * n + j) + 1] = 0.0; }
-      __syncthreads();
+      const double ip = 1.0 / piv;
       const int rem = n - j - 1;
       for (int e = t; e < rem * rem; e += NT) {
         const int i = j + 1 + e / rem, k = j + 1 + e % rem;
         if (k > i) continue;
         cd v = ldc(L, i * n + k);
-        cfms_aconjb(v, ldc(L, i * n + j), ldc(L, k * n + j));
+        cfms_aconjb(v, cscale(ldc(L, i * n + j), ip), ldc(L, k * n + j));
         stc(L, i * n + k, v);
       }
+      if (j > 0)
+        for (int i = j + t; i < n; i += NT) stc(L, i * n + j - 1, cscale(ldc(L, i * n + j - 1), inv[j - 1]));
+      if (t == 0) inv[j] = 1.0 / sqrt(piv);
       __syncthreads();
     }
-    // x = L^-H L^-1 c: column-oriented substitutions, threads over (row, channel)
-    for (int k = 0; k < n; ++k) {
-      const double inv = 1.0 / L[2 * (k * n + k)];
-      if (t < C) stc(x, k * C + t, cscale(ldc(x, k * C + t), inv));
-      __syncthreads();
-      for (int e = t; e < (n - k - 1) * C; e += NT) {
-        const int i = k + 1 + e / C, c = e % C;
-        stc(x, i * C + c, csub(ldc(x, i * C + c), cmul(ldc(L, i * n + k), ldc(x, k * C + c))));
+
+    // Triangular sweeps over a set of right-hand-side columns: the C
+    // right-hand sides of x and, for the leave-one-out loss, the m columns of
+    // P = conj(A)^T (so that P becomes L^-1 A^H, then G = L^-H P).  Each step
+    // updates with the final row k and scales the row that became final, so
+    // one barrier per step.
+    double* Pm = sm + o.P;
+    const int ncol = C + (P.mode == 1 ? m : 0);
+    auto el = [&](int i, int col) -> double* { return col < C ? x + 2 * (i * C + col) : Pm + 2 * (i * m + col - C); };
+    if (P.mode == 1) {
+      for (int e = t; e < n * m; e += NT) {
+        const int k = e / m, j = e - k * m;
+        stc(Pm, e, cd{A[2 * (j * n + k)], -A[2 * (j * n + k) + 1]});
       }
       __syncthreads();
     }
-    for (int k = n - 1; k >= 0; --k) {
-      const double inv = 1.0 / L[2 * (k * n + k)];
-      if (t < C) stc(x, k * C + t, cscale(ldc(x, k * C + t), inv));
+    // forward: row 0 scaled, then steps k = 0 .. n-2
+    for (int col = t; col < ncol; col += NT) stc(el(0, col), 0, cscale(ldc(el(0, col), 0), inv[0]));
+    __syncthreads();
+    for (int k = 0; k + 1 < n; ++k) {
+      for (int e = t; e < (n - k - 1) * ncol; e += NT) {
+        const int i = k + 1 + e / ncol, col = e % ncol;
+        cd v = csub(ldc(el(i, col), 0), cmul(ldc(L, i * n + k), ldc(el(k, col), 0)));
+        if (i == k + 1) v = cscale(v, inv[i]);
+        stc(el(i, col), 0, v);
+      }
       __syncthreads();
-      for (int e = t; e < k * C; e += NT) {
-        const int i = e / C, c = e % C;
-        stc(x, i * C + c, csub(ldc(x, i * C + c), cmulc(ldc(L, k * n + i), ldc(x, k * C + c))));
+    }
+    double hj = 0.0;
+    if (P.mode == 1 && t < m) {
+      for (int k = 0; k < n; ++k) {
+        const cd v = ldc(Pm, k * m + t);
+        hj += v.re * v.re + v.im * v.im;
+      }
+    }
+    // backward: row n-1 scaled, then steps k = n-1 .. 1
+    for (int col = t; col < ncol; col += NT) stc(el(n - 1, col), 0, cscale(ldc(el(n - 1, col), 0), inv[n - 1]));
+    __syncthreads();
+    for (int k = n - 1; k > 0; --k) {
+      for (int e = t; e < k * ncol; e += NT) {
+        const int i = e / ncol, col = e % ncol;
+        cd v = csub(ldc(el(i, col), 0), cmulc(ldc(L, k * n + i), ldc(el(k, col), 0)));
+        if (i == k - 1) v = cscale(v, inv[i]);
+        stc(el(i, col), 0, v);
       }
       __syncthreads();
     }
@@ -178,6 +230,7 @@ __global__ __launch_bounds__(256) void k_calib(CalibParams P) {
     for (int i = t; i < m * C; i += NT) {
       const int j = i / C, c = i - j * C;
       cd s = cd{0.0, 0.0};
+      #pragma unroll 4
       for (int k = 0; k < n; ++k) cfma(s, ldc(A, j * n + k), ldc(x, k * C + c));
       s = csub(s, ldc(b, i));
       stc(r, i, cscale(s, rs));
@@ -207,60 +260,28 @@ __global__ __launch_bounds__(256) void k_calib(CalibParams P) {
         T[i] = 4.0 * kPi * s;
       }
     } else {
-      double* Pm = sm + o.P;
       double* w = sm + o.w;
       double* y = sm + o.y;
       double* v = sm + o.v;
       double* gam = sm + o.gam;
       double* Wm = sm + o.Wm;
-      // P = L^-1 A^H, then G = L^-H P in place: column-oriented substitutions,
-      // threads over (row, view); h_j = ||P_:j||^2 between the two sweeps
-      for (int e = t; e < n * m; e += NT) {
-        const int k = e / m, j = e - k * m;
-        stc(Pm, e, cd{A[2 * (j * n + k)], -A[2 * (j * n + k) + 1]});
-      }
-      __syncthreads();
-      for (int k = 0; k < n; ++k) {
-        const double inv = 1.0 / L[2 * (k * n + k)];
-        for (int j = t; j < m; j += NT) stc(Pm, k * m + j, cscale(ldc(Pm, k * m + j), inv));
-        __syncthreads();
-        for (int e = t; e < (n - k - 1) * m; e += NT) {
-          const int i = k + 1 + e / m, j = e % m;
-          stc(Pm, i * m + j, csub(ldc(Pm, i * m + j), cmul(ldc(L, i * n + k), ldc(Pm, k * m + j))));
-        }
-        __syncthreads();
-      }
-      for (int j = t; j < m; j += NT) {
-        double h = 0.0;
-        for (int k = 0; k < n; ++k) {
-          const cd v = ldc(Pm, k * m + j);
-          h += v.re * v.re + v.im * v.im;
-        }
-        const double om = 1.0 - h;
+      if (t < m) {
+        const double om = 1.0 - hj;
         double rr = 0.0;
         for (int c = 0; c < C; ++c) {
-          const cd rv = ldc(r, j * C + c);
+          const cd rv = ldc(r, t * C + c);
           rr += rv.re * rv.re + rv.im * rv.im;
-          stc(w, j * C + c, cscale(rv, 1.0 / (om * om)));
+          stc(w, t * C + c, cscale(rv, 1.0 / (om * om)));
         }
         loss += rr / (om * om);
-        gam[j] = 2.0 * rr / (om * om * om);
+        gam[t] = 2.0 * rr / (om * om * om);
       }
       __syncthreads();
-      for (int k = n - 1; k >= 0; --k) {
-        const double inv = 1.0 / L[2 * (k * n + k)];
-        for (int j = t; j < m; j += NT) stc(Pm, k * m + j, cscale(ldc(Pm, k * m + j), inv));
-        __syncthreads();
-        for (int e = t; e < k * m; e += NT) {
-          const int i = e / m, j = e % m;
-          stc(Pm, i * m + j, csub(ldc(Pm, i * m + j), cmulc(ldc(L, k * n + i), ldc(Pm, k * m + j))));
-        }
-        __syncthreads();
-      }
       // y = G w
       for (int i = t; i < n * C; i += NT) {
         const int k = i / C, c = i - k * C;
         cd s = cd{0.0, 0.0};
+        #pragma unroll 4
         for (int j = 0; j < m; ++j) cfma(s, ldc(Pm, k * m + j), ldc(w, j * C + c));
         stc(y, i, s);
       }
@@ -268,6 +289,7 @@ __global__ __launch_bounds__(256) void k_calib(CalibParams P) {
       for (int e = t; e < n * n; e += NT) {
         const int p = e / n, k = e - p * n;
         cd s = cd{0.0, 0.0};
+        #pragma unroll 4
         for (int i = 0; i < m; ++i) cfma(s, cscale(ldc(A, i * n + p), gam[i]), ldc(Pm, k * m + i));
         stc(Wm, e, s);
       }
@@ -289,6 +311,7 @@ __global__ __launch_bounds__(256) void k_calib(CalibParams P) {
           psi = csub(psi, cmulc(vv, xx));
           psi = csub(psi, cmulc(rr, yy));
         }
+        #pragma unroll 4
         for (int p = 0; p < n; ++p) psi = csub(psi, cmul(ldc(Pm, p * m + j), ldc(Wm, p * n + k)));
         const cd pa = cmul(psi, ldc(A, i));
         T[i] = -4.0 * kPi * pa.im;
@@ -298,12 +321,14 @@ __global__ __launch_bounds__(256) void k_calib(CalibParams P) {
     // accumulate the chain rule through theta_jk = d_k <u_j, w>
     if (t < m) {
       double g = 0.0;
+      #pragma unroll 4
       for (int k = 0; k < n; ++k) g += (double)P.d[k] * T[t * n + k];
       gu[0] += g * wx;
       gu[1] += g * wy;
     }
     if (t < n) {
       double g = 0.0;
+      #pragma unroll 4
       for (int j = 0; j < m; ++j) g += T[j * n + t] * pj[j];
       gd += g;
     }
