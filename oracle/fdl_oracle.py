@@ -34,6 +34,11 @@ Readings of the paper used here (each stated where it is used):
       Eq. CalibrationProb, the SUM over the sampled frequencies (the
       stochastic subset replaces the full sum); the update uses ||grad||^2
       as printed.
+* R5  relaxed model (Sec. VIII-B): in 2D the shift of layer k in view j is a
+      pair P_jk = (P^x_jk, P^y_jk), rank-1 case P_jk = d_k u_j; the phase is
+      <P_jk, w>; grad P^x = sum_q G_jk w_x, grad P^y = sum_q G_jk w_y (Eq. gradP
+      with both components); the update normalises by the squared norm over all
+      2mn entries; the regulariser must not depend on d (LAYER2 or L2).
 """
 from __future__ import annotations
 
@@ -413,6 +418,149 @@ def gd_step(u: np.ndarray, d: np.ndarray, grad_u: np.ndarray, grad_d: np.ndarray
     u2 = np.asarray(u, dtype=np.float64) - alpha * gu / (eps_g + np.sum(gu * gu))
     d2 = np.asarray(d, dtype=np.float64) - alpha * gd / (eps_g + np.sum(gd * gd))
     return u2, d2
+
+
+# ---------------------------------------------------------------------------
+# Relaxed FDL model (Sec. VIII-B, denoising): a free shift for every pair of
+# input view and layer instead of the rank-1 product d_k u_j (reading R5)
+# ---------------------------------------------------------------------------
+
+def shifts_rank1(u: np.ndarray, d: np.ndarray) -> np.ndarray:
+    """P[j, k] = d_k u_j, the rank-1 shift matrix of the unrelaxed model,
+    [m, n, 2] float64 (last axis: horizontal, vertical)."""
+    u = np.asarray(u, dtype=np.float64)
+    d = np.asarray(d, dtype=np.float64)
+    return d[None, :, None] * u[:, None, :]
+
+
+def a_matrix_shifts(shifts: np.ndarray, wx: np.ndarray, wy: np.ndarray) -> np.ndarray:
+    """A[f, j, k] = exp(+2 pi i <P_jk, w_f>) for a free shift matrix
+    P [m, n, 2]; with P = :func:`shifts_rank1` this is :func:`a_matrix`."""
+    P = np.asarray(shifts, dtype=np.float64)
+    t = wx[:, None, None] * P[None, :, :, 0] + wy[:, None, None] * P[None, :, :, 1]
+    return np.exp(2j * math.pi * t)
+
+
+def _check_relaxed_reg(reg: int) -> None:
+    if reg not in (REG_LAYER2, REG_L2):
+        raise ValueError("the relaxed model has no layer disparities: use REG_LAYER2 or REG_L2")
+
+
+def construct_relaxed(view_spec: np.ndarray, shifts: np.ndarray, H: int, W: int,
+                      lam: float, eps: float, reg: int = REG_LAYER2,
+                      freq_index: Optional[np.ndarray] = None, chunk: int = 2048) -> np.ndarray:
+    """Layers of the relaxed model: the closed form of :func:`construct` with
+    A from :func:`a_matrix_shifts` (the layers are built "using the shifts
+    P_jk instead of u_j d_k", Sec. VIII-B).  Returns [n, C, H, W//2+1]
+    complex128, or [n, C, len(freq_index)]."""
+    _check_relaxed_reg(reg)
+    view_spec = np.asarray(view_spec)
+    m, C = view_spec.shape[:2]
+    n = np.asarray(shifts).shape[1]
+    wx_all, wy_all = flat_freqs(H, W)
+    b_all = view_spec.reshape(m, C, -1)
+    if freq_index is None:
+        freq_index = np.arange(wx_all.shape[0])
+    freq_index = np.asarray(freq_index, dtype=np.int64)
+    out = np.zeros((n, C, freq_index.shape[0]), dtype=np.complex128)
+    for s in range(0, freq_index.shape[0], chunk):
+        fi = freq_index[s:s + chunk]
+        wx, wy = wx_all[fi], wy_all[fi]
+        A = a_matrix_shifts(shifts, wx, wy)
+        M = normal_matrix(A, reg_matrix(reg, np.zeros(n), wx, wy), lam, eps)
+        b = np.transpose(b_all[:, :, fi], (2, 0, 1)).astype(np.complex128)
+        x = np.linalg.solve(M, np.conj(np.swapaxes(A, -1, -2)) @ b)
+        out[:, :, s:s + chunk] = np.transpose(x, (1, 2, 0))
+    if freq_index.shape[0] == wx_all.shape[0] and np.array_equal(freq_index, np.arange(wx_all.shape[0])):
+        return out.reshape(n, C, H, W // 2 + 1)
+    return out
+
+
+def render_relaxed(layer_spec: np.ndarray, shifts: np.ndarray, H: int, W: int) -> np.ndarray:
+    """The input views as the relaxed model predicts them (the denoised
+    result, Sec. VIII-B): B_j(w) = sum_k exp(+2 pi i <P_jk, w>) L_k(w) for
+    every row j of P [V, n, 2].  Returns [V, C, H, W//2+1] complex128."""
+    layer_spec = np.asarray(layer_spec)
+    n, C = layer_spec.shape[:2]
+    P = np.asarray(shifts, dtype=np.float64)
+    wx, wy = freq_grid(H, W)
+    out = np.zeros((P.shape[0], C) + wx.shape, dtype=np.complex128)
+    for j in range(P.shape[0]):
+        for k in range(n):
+            out[j] += np.exp(2j * math.pi * (P[j, k, 0] * wx + P[j, k, 1] * wy))[None] * layer_spec[k]
+    return out
+
+
+def calib_relaxed_fit_loss_grad(view_spec: np.ndarray, shifts: np.ndarray, H: int, W: int,
+                                lam: float, eps: float, reg: int, freq_index: np.ndarray):
+    """Objective of Eq. CalibrationProb as a function of a free shift matrix
+    and its gradient, Eq. gradP with both components (R5):
+    G_jk(q) = 4 pi Im(conj(x_k) conj(A_jk) r_j), r = A x - b,
+    grad P^x_jk = sum_q G_jk(q) w_x(q), grad P^y_jk = sum_q G_jk(q) w_y(q).
+    Returns (loss, grad_P [m, n, 2]) as float64."""
+    _check_relaxed_reg(reg)
+    P = np.asarray(shifts, dtype=np.float64)
+    n = P.shape[1]
+    wx, wy, b, R = _calib_system(view_spec, None, np.zeros(n), H, W, lam, eps, reg, freq_index)
+    A = a_matrix_shifts(P, wx, wy)
+    M = normal_matrix(A, R, lam, eps)
+    x = np.linalg.solve(M, np.conj(np.swapaxes(A, -1, -2)) @ b)
+    r = A @ x - b
+    Rfull = lam * R + eps * np.eye(n)[None]
+    loss = (np.sum(np.abs(r) ** 2)
+            + np.real(np.einsum("qkc,qkl,qlc->", np.conj(x), Rfull, x)))
+    G = 4.0 * math.pi * np.imag(np.conj(A) * np.einsum("qkc,qjc->qjk", np.conj(x), r))
+    grad = np.stack([np.einsum("qjk,q->jk", G, wx), np.einsum("qjk,q->jk", G, wy)], axis=-1)
+    return float(loss), grad
+
+
+def calib_relaxed_loo_loss_grad(view_spec: np.ndarray, shifts: np.ndarray, H: int, W: int,
+                                lam: float, eps: float, reg: int, freq_index: np.ndarray):
+    """Leave-one-out loss of the relaxed model (explicit refit without each
+    view, as :func:`calib_loo_loss`) and its gradient with respect to P by
+    reverse-mode automatic differentiation (torch autograd, complex128, CPU).
+    Returns (loss, grad_P [m, n, 2])."""
+    import torch
+
+    _check_relaxed_reg(reg)
+    P0 = np.asarray(shifts, dtype=np.float64)
+    n = P0.shape[1]
+    wx_np, wy_np, b_np, R_np = _calib_system(view_spec, None, np.zeros(n), H, W, lam, eps, reg, freq_index)
+    tP = torch.tensor(P0, requires_grad=True)
+    wx = torch.tensor(wx_np)
+    wy = torch.tensor(wy_np)
+    b = torch.tensor(b_np)
+    R = torch.tensor(R_np, dtype=torch.complex128)
+    m = tP.shape[0]
+    t = wx[:, None, None] * tP[None, :, :, 0] + wy[:, None, None] * tP[None, :, :, 1]
+    A = torch.exp(2j * math.pi * t.to(torch.complex128))
+    eye = torch.eye(n, dtype=torch.complex128)
+    total = torch.zeros((), dtype=torch.float64)
+    for j in range(m):
+        keep = [i for i in range(m) if i != j]
+        Aj = A[:, keep, :]
+        Ajh = Aj.conj().transpose(-1, -2)
+        x = torch.linalg.solve(Ajh @ Aj + lam * R + eps * eye, Ajh @ b[:, keep, :])
+        pred = torch.einsum("qk,qkc->qc", A[:, j, :], x)
+        total = total + torch.sum(torch.abs(b[:, j, :] - pred) ** 2)
+    total.backward()
+    return float(total.detach()), tP.grad.numpy().copy()
+
+
+def calib_relaxed_loss_grad(view_spec, shifts, H, W, lam, eps, reg, mode, freq_index):
+    """Dispatch on the loss mode for the relaxed model."""
+    if mode == LOSS_FIT:
+        return calib_relaxed_fit_loss_grad(view_spec, shifts, H, W, lam, eps, reg, freq_index)
+    if mode == LOSS_LOO:
+        return calib_relaxed_loo_loss_grad(view_spec, shifts, H, W, lam, eps, reg, freq_index)
+    raise ValueError(f"unknown loss mode {mode}")
+
+
+def gd_step_relaxed(shifts: np.ndarray, grad: np.ndarray, alpha: float = 0.2, eps_g: float = 1e-6) -> np.ndarray:
+    """P' = P - alpha grad_P / (eps + ||grad_P||^2), the update of Sec. V-B
+    applied to the whole shift matrix (R5)."""
+    g = np.asarray(grad, dtype=np.float64)
+    return np.asarray(shifts, dtype=np.float64) - alpha * g / (eps_g + np.sum(g * g))
 
 
 def rel_l2(y: np.ndarray, ref: np.ndarray) -> float:

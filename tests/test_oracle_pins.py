@@ -400,3 +400,139 @@ def test_construct_views_recovers_layers_from_a_focal_stack():
     inputs = O.render(spec, d, views, H, W)
     x = O.construct_views(inputs, views, d, H, W, 1e-12, 1e-12, O.REG_L2)
     assert O.rel_l2(x, spec) < 1e-7
+
+
+# ------------------------------------------------ relaxed model (Sec. VIII-B) ------
+
+def _relaxed_case(seed=21, m=5, n=3, H=8, W=8, C=1):
+    """A shift matrix that is far from rank 1, plus random input spectra."""
+    rng = np.random.default_rng(seed)
+    P = rng.uniform(-2.0, 2.0, (m, n, 2))
+    spec = O.rfft2(rng.standard_normal((m, C, H, W)))
+    F = H * (W // 2 + 1)
+    return P, spec, np.arange(1, F)
+
+
+@pytest.mark.parametrize("reg", [O.REG_LAYER2, O.REG_L2])
+def test_relaxed_construct_matches_stacked_least_squares(reg):
+    H, W = 8, 8
+    P, spec, _ = _relaxed_case(C=2)
+    m, n = P.shape[:2]
+    lam, eps = 0.2, 1e-2
+    x = O.construct_relaxed(spec, P, H, W, lam, eps, reg)
+    wx, wy = O.freq_grid(H, W)
+    Gam = O.second_difference(n) if reg == O.REG_LAYER2 else np.eye(n)
+    for ky in range(H):
+        for kx in range(W // 2 + 1):
+            A = np.zeros((m, n), dtype=np.complex128)
+            for j in range(m):
+                for k in range(n):
+                    A[j, k] = cmath.exp(2j * math.pi * (P[j, k, 0] * wx[ky, kx] + P[j, k, 1] * wy[ky, kx]))
+            ref = brute.stacked_lstsq(A, spec[:, :, ky, kx], Gam, lam, eps)
+            np.testing.assert_allclose(x[:, :, ky, kx], ref, rtol=1e-9, atol=1e-9)
+
+
+def test_relaxed_construct_rejects_the_view_regulariser():
+    P, spec, _ = _relaxed_case()
+    with pytest.raises(ValueError):
+        O.construct_relaxed(spec, P, 8, 8, 0.1, 1e-3, O.REG_VIEW2)
+
+
+def test_relaxed_render_integer_shifts_is_sum_of_rolls():
+    """B_j = sum_k L_k shifted by the integer pair P_jk, done as circular
+    shifts of the spatial layers (no Fourier arithmetic)."""
+    H, W = 12, 16
+    rng = np.random.default_rng(22)
+    layers = rng.standard_normal((3, 2, H, W))
+    P = rng.integers(-3, 4, (4, 3, 2)).astype(float)
+    img = O.irfft2(O.render_relaxed(O.rfft2(layers), P, H, W), H, W)
+    ref = np.zeros((4, 2, H, W))
+    for j in range(4):
+        for k in range(3):
+            ref[j] += np.roll(layers[k], (-int(P[j, k, 1]), -int(P[j, k, 0])), axis=(-2, -1))
+    np.testing.assert_allclose(img, ref, atol=1e-12)
+
+
+def test_relaxed_model_data_is_reproduced():
+    """Views made by the relaxed model itself (integer shifts, not rank 1):
+    the layers built with those shifts and lambda, eps -> 0 render the inputs
+    back, while the best rank-1 model of the same size cannot."""
+    H, W = 16, 16
+    rng = np.random.default_rng(23)
+    n = 4
+    layers = rng.standard_normal((n, 1, H, W))
+    u_int = [(a, b) for b in (-1, 0, 1) for a in (-1, 0, 1)]
+    d_int = [-2, -1, 1, 2]
+    P = O.shifts_rank1(np.array(u_int, float), np.array(d_int, float))
+    P[0, 0] += (1, 0)      # two occlusion-like deviations from P = u d^T
+    P[8, 3] += (0, -1)
+    views = np.zeros((9, 1, H, W))
+    for j in range(9):
+        for k in range(n):
+            views[j] += np.roll(layers[k], (-int(P[j, k, 1]), -int(P[j, k, 0])), axis=(-2, -1))
+    x = O.construct_relaxed(O.rfft2(views), P, H, W, 1e-12, 1e-12, O.REG_L2)
+    back = O.irfft2(O.render_relaxed(x, P, H, W), H, W)
+    assert O.rel_l2(back, views) < 1e-6
+    u = np.array(u_int, float)
+    d = np.array(d_int, float)
+    x1 = O.construct(O.rfft2(views), u, d, H, W, 1e-12, 1e-12, O.REG_L2)
+    rv = np.zeros((9, 5))
+    rv[:, :2] = u
+    assert O.rel_l2(O.render_images(x1, d, rv, H, W), views) > 1e-2
+
+
+@pytest.mark.parametrize("mode", [O.LOSS_FIT, O.LOSS_LOO])
+def test_relaxed_gradient_of_rank1_shifts_gives_the_calibration_gradient(mode):
+    """With P = u d^T the chain rule through P_jk = d_k u_j turns grad P into
+    grad u_j = sum_k d_k grad P_jk and grad d_k = sum_j <u_j, grad P_jk>
+    (Eqs. gradD, gradP), which must equal the finite-difference-pinned
+    calibration gradients."""
+    H, W = 8, 8
+    rng = np.random.default_rng(24)
+    u = rng.uniform(-1.5, 1.5, (5, 2))
+    d = np.sort(rng.uniform(-1.5, 1.5, 3))
+    spec = O.rfft2(rng.standard_normal((5, 1, H, W)))
+    S = np.arange(1, H * (W // 2 + 1), 2)
+    lam, eps = 1e-2, 1e-3
+    loss, gu, gd = O.calib_loss_grad(spec, u, d, H, W, lam, eps, O.REG_LAYER2, mode, S)
+    lossP, gP = O.calib_relaxed_loss_grad(spec, O.shifts_rank1(u, d), H, W, lam, eps, O.REG_LAYER2, mode, S)
+    assert abs(loss - lossP) < 1e-12 * abs(loss)
+    np.testing.assert_allclose(np.einsum("jkc,k->jc", gP, d), gu, rtol=1e-9, atol=1e-12 * np.abs(gu).max())
+    np.testing.assert_allclose(np.einsum("jkc,jc->k", gP, u), gd, rtol=1e-9, atol=1e-12 * np.abs(gd).max())
+
+
+def test_relaxed_fit_gradient_matches_finite_differences():
+    H, W = 8, 8
+    P, spec, S = _relaxed_case(seed=25, m=4, n=3)
+    lam, eps = 1e-2, 1e-3
+    _, g = O.calib_relaxed_fit_loss_grad(spec, P, H, W, lam, eps, O.REG_LAYER2, S)
+    fd = brute.central_fd(lambda PP: O.calib_relaxed_fit_loss_grad(spec, PP, H, W, lam, eps, O.REG_LAYER2, S)[0], P)
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-9 * np.abs(fd).max())
+
+
+def test_relaxed_loo_gradient_matches_finite_differences():
+    H, W = 8, 8
+    P, spec, S = _relaxed_case(seed=26, m=4, n=2)
+    S = S[::3]
+    lam, eps = 1e-2, 1e-3
+    _, g = O.calib_relaxed_loo_loss_grad(spec, P, H, W, lam, eps, O.REG_L2, S)
+
+    def loo(PP):
+        # the leave-one-out loss straight from its definition: one refit per left-out view
+        wx, wy = O.flat_freqs(H, W)
+        m, C = spec.shape[:2]
+        tot = 0.0
+        for f in S:
+            A = O.a_matrix_shifts(PP, wx[f:f + 1], wy[f:f + 1])[0]
+            b = spec.reshape(m, C, -1)[:, :, f] / math.sqrt(H * W)
+            tot += np.sum(np.abs(brute.press_residuals(A, b, np.eye(PP.shape[1]), lam, eps)) ** 2)
+        return tot
+
+    fd = brute.central_fd(loo, P)
+    np.testing.assert_allclose(g, fd, rtol=1e-6, atol=1e-9 * np.abs(fd).max())
+
+
+def test_relaxed_gd_step_hand_values():
+    P2 = O.gd_step_relaxed(np.array([[[1.0, 0.0]], [[0.0, 1.0]]]), np.array([[[2.0, 0.0]], [[0.0, 0.0]]]),
+                           alpha=0.2, eps_g=0.0)
+    np.testing.assert_allclose(P2, [[[0.9, 0.0]], [[0.0, 1.0]]])
