@@ -277,6 +277,44 @@ int fdl_batch_plan_set_tuning(fdl_batch_plan* plan, int32_t mode, int32_t chunk,
 int fdl_batch_plan_destroy(fdl_batch_plan* plan);
 
 /* ---------------------------------------------------------------------------
+ * Relaxed FDL model (Sec. VIII-B, denoising).  The shift of layer k in input
+ * view j is a free pair P_jk = (P^x_jk, P^y_jk) instead of the rank-1 product
+ * d_k u_j, so that occlusions and non-Lambertian effects can be absorbed:
+ *   A_jk(w) = exp(+2 pi i <P_jk, w>).
+ * shifts_dev: [m][n] fdl_f2 on the device (row j: the n shifts of view j);
+ * the rank-1 model is P_jk = d_k u_j.  There are no layer disparities, so the
+ * regulariser must be FDL_REG_LAYER2 or FDL_REG_L2 (FDL_EINVAL otherwise).
+ *
+ * fdl_construct_relaxed: layers x = (A^H A + lambda R + eps I)^-1 A^H b per
+ *   bin, as fdl_construct (same layouts, status and limits) with A from P;
+ *   the Gram matrix is always formed from all n(n+1)/2 products.
+ * fdl_render_relaxed: the input views as the model predicts them (the
+ *   denoised result): out_j(w) = sum_k exp(2 pi i <P_jk, w>) L_k(w) for the V
+ *   rows of shifts_dev ([V][n]); out_spec_dev [V][C][H][W/2+1], FP32 phases.
+ * fdl_calib_grad_relaxed: the calibration loss of fdl_calib_grad (FIT or
+ *   LOO, same bins, scaling and limits) as a function of P, and its gradient
+ *   (Eq. gradP with both components): grad P^x_jk = sum_q T_jk(q) w_x(q),
+ *   grad P^y_jk = sum_q T_jk(q) w_y(q), T_jk = dE_q / d<P_jk, w_q>.
+ *   grad_shifts_dev [m][n][2] double; loss_dev [1] double; workspace of at
+ *   least fdl_calib_relaxed_workspace(m, n, Q) bytes; the per-bin LDS of
+ *   fdl_calib_grad plus 16 m n bytes must fit one block (FDL_ESHAPE).
+ * fdl_gd_step_relaxed: P <- P - alpha grad_P / (eps_g + ||grad_P||^2), the
+ *   update of Sec. V-B with the norm over all 2 m n entries, in FP64, stored
+ *   back to the float shifts (m n <= 2^24).
+ * ------------------------------------------------------------------------- */
+int fdl_construct_relaxed(const fdl_c64* view_spec_dev, const fdl_f2* shifts_dev, int m, int n, int C, int H, int W,
+                          float lambda, float eps, int reg, fdl_c64* layer_spec_dev, int32_t* status_dev,
+                          void* stream);
+int fdl_render_relaxed(const fdl_c64* layer_spec_dev, const fdl_f2* shifts_dev, int n, int C, int H, int W, int V,
+                       fdl_c64* out_spec_dev, void* stream);
+size_t fdl_calib_relaxed_workspace(int m, int n, int Q);
+int fdl_calib_grad_relaxed(const fdl_c64* view_spec_dev, const fdl_f2* shifts_dev, int m, int n, int C, int H, int W,
+                           float lambda, float eps, int reg, int mode, const int32_t* freq_idx_dev, int Q,
+                           double* loss_dev, double* grad_shifts_dev, void* ws_dev, size_t ws_bytes, void* stream);
+int fdl_gd_step_relaxed(fdl_f2* shifts_dev, const double* grad_shifts_dev, int m, int n, double alpha, double eps_g,
+                        void* stream);
+
+/* ---------------------------------------------------------------------------
  * Measurement utility (not part of the method): enqueues `blocks` blocks of
  * 256 threads, each thread running 8 independent FP64 multiply-add chains of
  * `iters` steps (16 * iters flops per thread) and writing one double to

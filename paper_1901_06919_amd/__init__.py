@@ -91,6 +91,17 @@ def lib():
         L.fdl_batch_plan_set_tuning.argtypes = [vp, i32, i32, i32]
     L.fdl_fma64_probe.restype = i32
     L.fdl_fma64_probe.argtypes = [vp, i32, i32, vp]
+    L.fdl_construct_relaxed.restype = i32
+    L.fdl_construct_relaxed.argtypes = [vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, vp, vp, vp]
+    L.fdl_render_relaxed.restype = i32
+    L.fdl_render_relaxed.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
+    L.fdl_calib_relaxed_workspace.restype = sz
+    L.fdl_calib_relaxed_workspace.argtypes = [i32, i32, i32]
+    L.fdl_calib_grad_relaxed.restype = i32
+    L.fdl_calib_grad_relaxed.argtypes = [vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, i32, vp, i32,
+                                         vp, vp, vp, sz, vp]
+    L.fdl_gd_step_relaxed.restype = i32
+    L.fdl_gd_step_relaxed.argtypes = [vp, vp, i32, i32, f64, f64, vp]
     _lib = L
     return L
 
@@ -270,6 +281,91 @@ def gd_step(u: torch.Tensor, d: torch.Tensor, grad_u: torch.Tensor, grad_d: torc
     _check(grad_d, torch.float64, (n,), "grad_d")
     _call("fdl_gd_step", u.data_ptr(), d.data_ptr(), grad_u.data_ptr(), grad_d.data_ptr(), m, n,
           float(alpha), float(eps_g), _stream(u))
+
+
+# ---- relaxed model (Sec. VIII-B): a free shift pair per view and layer ----
+
+def _check_shifts(shifts: torch.Tensor, rows: int, n: int):
+    _check(shifts, torch.float32, (rows, n, 2), "shifts")
+
+
+def construct_relaxed(view_spec: torch.Tensor, shifts: torch.Tensor, H: int, W: int, lam: float, eps: float,
+                      reg: int = REG_LAYER2, out: Optional[torch.Tensor] = None,
+                      status: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Layer spectra [n, C, H, W//2+1] of the relaxed model from view spectra
+    [m, C, H, W//2+1] and shifts [m, n, 2] float32 (fdl_construct_relaxed)."""
+    m, C = view_spec.shape[:2]
+    n = shifts.shape[1]
+    _check(view_spec, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
+    _check_shifts(shifts, m, n)
+    if out is None:
+        out = torch.empty((n, C, H, W // 2 + 1), dtype=torch.complex64, device=view_spec.device)
+    _check(out, torch.complex64, (n, C, H, W // 2 + 1), "out")
+    sp = 0
+    if status is not None:
+        _check(status, torch.int32, (1,), "status")
+        sp = status.data_ptr()
+    _call("fdl_construct_relaxed", view_spec.data_ptr(), shifts.data_ptr(), m, n, C, H, W, float(lam), float(eps),
+          int(reg), out.data_ptr(), sp, _stream(view_spec))
+    return out
+
+
+def render_relaxed(layer_spec: torch.Tensor, shifts: torch.Tensor, H: int, W: int,
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Spectra [V, C, H, W//2+1] of the views whose shift rows are
+    shifts [V, n, 2] (fdl_render_relaxed)."""
+    n, C = layer_spec.shape[:2]
+    V = shifts.shape[0]
+    _check(layer_spec, torch.complex64, (n, C, H, W // 2 + 1), "layer_spec")
+    _check_shifts(shifts, V, n)
+    if out is None:
+        out = torch.empty((V, C, H, W // 2 + 1), dtype=torch.complex64, device=layer_spec.device)
+    _check(out, torch.complex64, (V, C, H, W // 2 + 1), "out")
+    _call("fdl_render_relaxed", layer_spec.data_ptr(), shifts.data_ptr(), n, C, H, W, V, out.data_ptr(),
+          _stream(layer_spec))
+    return out
+
+
+def calib_relaxed_workspace_bytes(m: int, n: int, Q: int) -> int:
+    return int(lib().fdl_calib_relaxed_workspace(m, n, Q))
+
+
+def calib_grad_relaxed(view_spec: torch.Tensor, shifts: torch.Tensor, H: int, W: int, lam: float, eps: float,
+                       reg: int, mode: int, freq_idx: Optional[torch.Tensor] = None,
+                       out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, ws: Optional[torch.Tensor] = None):
+    """(loss [1] f64, grad_shifts [m, n, 2] f64) (fdl_calib_grad_relaxed)."""
+    m, C = view_spec.shape[:2]
+    n = shifts.shape[1]
+    _check(view_spec, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
+    _check_shifts(shifts, m, n)
+    dev = view_spec.device
+    if freq_idx is not None:
+        _check(freq_idx, torch.int32, None, "freq_idx")
+        Q = freq_idx.numel()
+        fp = freq_idx.data_ptr()
+    else:
+        Q = H * (W // 2 + 1)
+        fp = 0
+    if out is None:
+        out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((m, n, 2), dtype=torch.float64, device=dev))
+    loss, g = out
+    _check(loss, torch.float64, (1,), "loss")
+    _check(g, torch.float64, (m, n, 2), "grad_shifts")
+    need = calib_relaxed_workspace_bytes(m, n, Q)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _call("fdl_calib_grad_relaxed", view_spec.data_ptr(), shifts.data_ptr(), m, n, C, H, W, float(lam), float(eps),
+          int(reg), int(mode), fp, Q, loss.data_ptr(), g.data_ptr(), ws.data_ptr(), ws.numel(), _stream(view_spec))
+    return loss, g
+
+
+def gd_step_relaxed(shifts: torch.Tensor, grad: torch.Tensor, alpha: float = 0.2, eps_g: float = 1e-6) -> None:
+    """In-place normalised gradient step on shifts [m, n, 2] f32 (fdl_gd_step_relaxed)."""
+    m, n = shifts.shape[:2]
+    _check_shifts(shifts, m, n)
+    _check(grad, torch.float64, (m, n, 2), "grad")
+    _call("fdl_gd_step_relaxed", shifts.data_ptr(), grad.data_ptr(), m, n, float(alpha), float(eps_g),
+          _stream(shifts))
 
 
 def fma64_probe(out: torch.Tensor, iters: int) -> float:

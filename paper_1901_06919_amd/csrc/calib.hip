@@ -28,11 +28,11 @@
 namespace fdl {
 
 struct CalibLayout {   // offsets (in doubles) into the dynamic LDS of one block
-  int A, L, inv, b, x, r, p, T, P, w, y, v, gam, Wm, red;
+  int A, L, inv, b, x, r, p, T, P, w, y, v, gam, Wm, gP, red;
   int total;
 };
 
-__host__ __device__ inline CalibLayout calib_layout(int m, int n, int C, int mode) {
+__host__ __device__ inline CalibLayout calib_layout(int m, int n, int C, int mode, bool relaxed) {
   CalibLayout o;
   int at = 0;
   o.A = at; at += 2 * m * n;
@@ -53,12 +53,16 @@ __host__ __device__ inline CalibLayout calib_layout(int m, int n, int C, int mod
   } else {
     o.P = o.w = o.y = o.v = o.gam = o.Wm = 0;
   }
+  o.gP = at;   // relaxed model: running gradient of the shifts, [m][n][2]
+  if (relaxed) at += 2 * m * n;
   o.red = at; at += 256;
   o.total = at;
   return o;
 }
 
-size_t calib_lds_bytes(int m, int n, int C, int mode) { return (size_t)calib_layout(m, n, C, mode).total * 8; }
+size_t calib_lds_bytes(int m, int n, int C, int mode, bool relaxed) {
+  return (size_t)calib_layout(m, n, C, mode, relaxed).total * 8;
+}
 
 __device__ __forceinline__ cd ldc(const double* s, int i) { return cd{s[2 * i], s[2 * i + 1]}; }
 __device__ __forceinline__ void stc(double* s, int i, cd v) { s[2 * i] = v.re; s[2 * i + 1] = v.im; }
@@ -82,11 +86,15 @@ __device__ __forceinline__ double reg_entry(int reg, int i, int k, int n, double
 // leaves room for 3 (as many as the leave-one-out LDS of 49 views and 16
 // layers allows).  Asking for 3 forces a tighter allocation that measured
 // slower; inner loops are unrolled by 4 (8 measured slower too).
+// RELAXED: the relaxed model of Sec. VIII-B, phases <P_jk, w> from a free
+// shift matrix and the gradient with respect to every shift (Eq. gradP with
+// both components) instead of the chain rule to u and d.
+template <bool RELAXED>
 __global__ __launch_bounds__(256, 2) void k_calib(CalibParams P) {
   constexpr int NT = 256;
   extern __shared__ double sm[];
   const int m = P.m, n = P.n, C = P.C;
-  const CalibLayout o = calib_layout(m, n, C, P.mode);
+  const CalibLayout o = calib_layout(m, n, C, P.mode, RELAXED);
   double* A = sm + o.A;
   double* L = sm + o.L;
   double* b = sm + o.b;
@@ -104,7 +112,10 @@ __global__ __launch_bounds__(256, 2) void k_calib(CalibParams P) {
   // The positions are the same for every bin: thread j keeps u_j.  The
   // spectra of the next bin (m C <= 1024 values, at most 4 per thread) are
   // loaded while the current bin is processed.
-  const float2 uj = t < m ? P.u[t] : make_float2(0.0f, 0.0f);
+  const float2 uj = !RELAXED && t < m ? P.u[t] : make_float2(0.0f, 0.0f);
+  double* gP = sm + o.gP;
+  if constexpr (RELAXED)
+    for (int i = t; i < 2 * m * n; i += NT) gP[i] = 0.0;
   float2 bnext[4];
   auto fetch = [&](int q) {
     if (q >= P.Q) return;
@@ -133,7 +144,12 @@ __global__ __launch_bounds__(256, 2) void k_calib(CalibParams P) {
     __syncthreads();
     for (int i = t; i < m * n; i += NT) {
       const int j = i / n, k = i - j * n;
-      stc(A, i, expi2pi((double)P.d[k] * pj[j]));
+      if constexpr (RELAXED) {
+        const float2 sh = P.shifts[i];
+        stc(A, i, expi2pi(fma((double)sh.x, wx, (double)sh.y * wy)));
+      } else {
+        stc(A, i, expi2pi((double)P.d[k] * pj[j]));
+      }
     }
     __syncthreads();
     // normal matrix (lower triangle, full storage) and right-hand sides
@@ -143,7 +159,7 @@ __global__ __launch_bounds__(256, 2) void k_calib(CalibParams P) {
       cd s = cd{0.0, 0.0};
       #pragma unroll 4
       for (int j = 0; j < m; ++j) cfma_conj(s, ldc(A, j * n + k1), ldc(A, j * n + k2));
-      s.re += reg_entry(P.reg, k1, k2, n, P.lambda, w4, (double)P.d[k1]) + (k1 == k2 ? P.eps : 0.0);
+      s.re += reg_entry(P.reg, k1, k2, n, P.lambda, w4, RELAXED ? 0.0 : (double)P.d[k1]) + (k1 == k2 ? P.eps : 0.0);
       if (k1 == k2) s.im = 0.0;
       stc(L, i, s);
     }
@@ -242,7 +258,8 @@ __global__ __launch_bounds__(256, 2) void k_calib(CalibParams P) {
       for (int i = t; i < m * C; i += NT) { const cd v = ldc(r, i); loss += v.re * v.re + v.im * v.im; }
       for (int i = t; i < n * n * C; i += NT) {
         const int c = i / (n * n), e = i - c * n * n, k1 = e / n, k2 = e - k1 * n;
-        const double g = reg_entry(P.reg, k1, k2, n, P.lambda, w4, (double)P.d[k1]) + (k1 == k2 ? P.eps : 0.0);
+        const double g =
+            reg_entry(P.reg, k1, k2, n, P.lambda, w4, RELAXED ? 0.0 : (double)P.d[k1]) + (k1 == k2 ? P.eps : 0.0);
         if (g != 0.0) {
           const cd a = ldc(x, k1 * C + c), bb = ldc(x, k2 * C + c);
           loss += g * (a.re * bb.re + a.im * bb.im);
@@ -318,24 +335,33 @@ __global__ __launch_bounds__(256, 2) void k_calib(CalibParams P) {
       }
     }
     __syncthreads();
-    // accumulate the chain rule through theta_jk = d_k <u_j, w>
-    if (t < m) {
-      double g = 0.0;
-      #pragma unroll 4
-      for (int k = 0; k < n; ++k) g += (double)P.d[k] * T[t * n + k];
-      gu[0] += g * wx;
-      gu[1] += g * wy;
-    }
-    if (t < n) {
-      double g = 0.0;
-      #pragma unroll 4
-      for (int j = 0; j < m; ++j) g += T[j * n + t] * pj[j];
-      gd += g;
+    if constexpr (RELAXED) {
+      // theta_jk = <P_jk, w>: grad P_jk += T_jk w (each thread keeps the
+      // entries it owns, so no barrier is needed between bins)
+      for (int i = t; i < m * n; i += NT) {
+        gP[2 * i] += T[i] * wx;
+        gP[2 * i + 1] += T[i] * wy;
+      }
+    } else {
+      // accumulate the chain rule through theta_jk = d_k <u_j, w>
+      if (t < m) {
+        double g = 0.0;
+        #pragma unroll 4
+        for (int k = 0; k < n; ++k) g += (double)P.d[k] * T[t * n + k];
+        gu[0] += g * wx;
+        gu[1] += g * wy;
+      }
+      if (t < n) {
+        double g = 0.0;
+        #pragma unroll 4
+        for (int j = 0; j < m; ++j) g += T[j * n + t] * pj[j];
+        gd += g;
+      }
     }
     __syncthreads();
   }
 
-  // block partials: [loss, grad_u (2m), grad_d (n)]
+  // block partials: [loss, grad_u (2m), grad_d (n)], relaxed [loss, grad_P (2mn)]
   double* red = sm + o.red;
   red[t] = loss;
   __syncthreads();
@@ -345,8 +371,12 @@ __global__ __launch_bounds__(256, 2) void k_calib(CalibParams P) {
     for (int i = 0; i < NT; ++i) s += red[i];
     out[0] = s;
   }
-  if (t < m) { out[1 + 2 * t] = gu[0]; out[2 + 2 * t] = gu[1]; }
-  if (t < n) out[1 + 2 * m + t] = gd;
+  if constexpr (RELAXED) {
+    for (int i = t; i < 2 * m * n; i += NT) out[1 + i] = gP[i];
+  } else {
+    if (t < m) { out[1 + 2 * t] = gu[0]; out[2 + 2 * t] = gu[1]; }
+    if (t < n) out[1 + 2 * m + t] = gd;
+  }
 }
 
 // One block per output value: each thread sums a strided subset of the block
@@ -365,6 +395,7 @@ __global__ __launch_bounds__(256) void k_calib_reduce(CalibParams P, int nblocks
   if (threadIdx.x == 0) {
     s = red[0];
     if (i == 0) P.loss[0] = s;
+    else if (P.shifts) P.grad_p[i - 1] = s;
     else if (i <= 2 * P.m) P.grad_u[i - 1] = s;
     else P.grad_d[i - 1 - 2 * P.m] = s;
   }
@@ -381,19 +412,25 @@ int calib_blocks(int Q, size_t lds_per_block) {
   return Q < (int)nb ? Q : (int)nb;
 }
 
-hipError_t launch_calib(const CalibParams& P, hipStream_t s) {
-  const size_t lds = calib_lds_bytes(P.m, P.n, P.C, P.mode);
+template <bool RELAXED>
+static hipError_t launch_calib_t(const CalibParams& P, hipStream_t s) {
+  const size_t lds = calib_lds_bytes(P.m, P.n, P.C, P.mode, RELAXED);
   const int nb = calib_blocks(P.Q, lds);
-  static size_t opted = 65536;
+  static size_t opted = 65536;   // per instantiation: the attribute is per kernel
   if (lds > opted) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_calib), hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_calib<RELAXED>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
     opted = lds;
   }
-  hipLaunchKernelGGL(k_calib, dim3(nb), dim3(256), lds, s, P);
+  hipLaunchKernelGGL(k_calib<RELAXED>, dim3(nb), dim3(256), lds, s, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_calib_reduce, dim3(P.stride), dim3(256), 0, s, P, nb);
   return hipGetLastError();
+}
+
+hipError_t launch_calib(const CalibParams& P, hipStream_t s) {
+  return P.shifts ? launch_calib_t<true>(P, s) : launch_calib_t<false>(P, s);
 }
 
 // Sec. V-B update, u' = u - alpha grad_u / (eps + ||grad_u||^2) (same for d).

@@ -220,10 +220,13 @@ __device__ __forceinline__ void team_transpose(TeamRows<R>& S, double2* tr, int 
 
 // APER: the inputs carry their own apertures (Eq. AMatGeneral):
 // A_jk = exp(2 pi i d_k p_j) psi_hat_j((s_j - d_k) w), general Gram path only.
-template <int R, int CT, bool TOEP, bool APER = false>
+// SHIFTS: the relaxed model (Sec. VIII-B), a free shift pair per view and
+// layer: A_jk = exp(2 pi i <P_jk, w>), general Gram path only.
+template <int R, int CT, bool TOEP, bool APER = false, bool SHIFTS = false>
 __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>& T, const double2* __restrict__ tab,
                                            int f, int lane) {
   static_assert(!(TOEP && APER), "apertures break the Toeplitz structure");
+  static_assert(!(SHIFTS && (TOEP || APER)), "free shifts use the general Gram path without apertures");
   // The system is padded to NMAX = 16 R unknowns with an identity block
   // (rows and columns >= n), so that every unrolled step below runs without
   // a branch on n: the padded unknowns have zero right-hand sides and solve
@@ -264,13 +267,20 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
   const float2* up = P.u + vzero;
   const float* vp = P.views + vzero;
+  const float2* sp = P.shifts + vzero;
   struct ViewIn {
     float2 u;
     float s, rho;
     int shape;
+    float2 sh[SHIFTS ? R : 1];
   };
   auto load = [&](int j, ViewIn& v, float2 (&b)[CT]) {
-    if constexpr (APER) {
+    if constexpr (SHIFTS) {
+      // the shifts of this lane's layers (padded layers read layer n - 1;
+      // their entries are replaced by the identity block)
+#pragma unroll
+      for (int r = 0; r < R; ++r) v.sh[r] = sp[(size_t)j * n + min(lane + 16 * r, n - 1)];
+    } else if constexpr (APER) {
       const float* q = vp + 5 * (size_t)j;
       v.u = make_float2(q[0], q[1]);
       v.s = q[2];
@@ -295,10 +305,17 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
     });
   }
   auto view = [&](const ViewIn& vj, const float2 (&bc)[CT]) {
-    const double p = fma((double)vj.u.x, wx, (double)vj.u.y * wy);
     cd A[R];
+    double p = 0.0;
+    if constexpr (SHIFTS) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) A[r] = expi_tab(tab, dt[r], p);
+      for (int r = 0; r < R; ++r)
+        A[r] = expi_tab(tab, (double)kPhaseTab, fma((double)vj.sh[r].x, wx, (double)vj.sh[r].y * wy));
+    } else {
+      p = fma((double)vj.u.x, wx, (double)vj.u.y * wy);
+#pragma unroll
+      for (int r = 0; r < R; ++r) A[r] = expi_tab(tab, dt[r], p);
+    }
     if constexpr (APER) {
       // the aperture of view j is the same in every lane of the wave
       const int shape = __builtin_amdgcn_readfirstlane(vj.shape);

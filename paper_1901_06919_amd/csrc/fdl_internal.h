@@ -12,6 +12,7 @@ struct ConstructParams {
   const float2* view_spec;   // [m][C][F]
   const float2* u;           // [m] positions (sub-aperture inputs)
   const float* views;        // [m][5] fdl_view records (inputs with apertures) or null
+  const float2* shifts = nullptr;   // [m][n] shift pairs of the relaxed model or null
   float2* layer_spec;        // [n][C][F]
   int* status;               // device counter or null
   int m, n, C, H, W, Wh, F;
@@ -26,6 +27,7 @@ struct RenderParams {
   const float2* layer_spec;  // [n][C][F]
   const float* d;            // [n]
   const void* views;         // [V] fdl_view (20 bytes each)
+  const float2* shifts = nullptr;   // [V][n] shift pairs of the relaxed model (fdl_render_relaxed)
   float2* out_spec;          // [V][C][F]
   int n, C, H, W, Wh, F, V;
 };
@@ -33,7 +35,9 @@ struct RenderParams {
 hipError_t launch_construct_r1(const ConstructParams& P, hipStream_t s);   // n <= 16
 hipError_t launch_construct_r2(const ConstructParams& P, hipStream_t s);   // n <= 32
 hipError_t launch_construct_views(const ConstructParams& P, hipStream_t s);   // inputs with apertures
+hipError_t launch_construct_relaxed(const ConstructParams& P, hipStream_t s);   // free shifts per view and layer
 hipError_t launch_render(const RenderParams& P, hipStream_t s);
+hipError_t launch_render_relaxed(const RenderParams& P, hipStream_t s);
 
 // Mixed-radix (4, 2, 3) plan for one FFT length.
 struct FftPlan {
@@ -63,12 +67,14 @@ struct CalibParams {
   double* loss;              // [1]
   double* grad_u;            // [m][2]
   double* grad_d;            // [n]
+  const float2* shifts = nullptr;   // [m][n] relaxed model, or null (rank 1: d_k u_j)
+  double* grad_p = nullptr;        // [m][n][2] relaxed model
   int m, n, C, H, W, Wh, F, Q;
   double lambda, eps, bscale;
   int reg, mode, stride;
 };
 
-size_t calib_lds_bytes(int m, int n, int C, int mode);
+size_t calib_lds_bytes(int m, int n, int C, int mode, bool relaxed = false);
 constexpr int kCalibMaxBlocks = 2048;
 int calib_blocks(int Q, size_t lds_per_block);
 hipError_t launch_calib(const CalibParams& P, hipStream_t s);

@@ -228,4 +228,98 @@ int fdl_gd_step(fdl_f2* u_dev, float* d_dev, const double* grad_u_dev, const dou
                                      eps_g, reinterpret_cast<hipStream_t>(stream)));
 }
 
+// ---- relaxed model (Sec. VIII-B): a free shift pair per view and layer ----
+
+int fdl_construct_relaxed(const fdl_c64* view_spec_dev, const fdl_f2* shifts_dev, int m, int n, int C, int H, int W,
+                          float lambda, float eps, int reg, fdl_c64* layer_spec_dev, int32_t* status_dev,
+                          void* stream) {
+  if (!view_spec_dev || !shifts_dev || !layer_spec_dev) return FDL_EINVAL;
+  if (!(std::isfinite(lambda) && lambda >= 0.f) || !(std::isfinite(eps) && eps >= 0.f)) return FDL_EINVAL;
+  if (reg != FDL_REG_LAYER2 && reg != FDL_REG_L2) return FDL_EINVAL;   // no disparities: no view regulariser
+  if (m < 1 || m > 4096 || n < 1 || n > FDL_MAX_LAYERS || C < 1 || C > FDL_MAX_CHANNELS) return FDL_ESHAPE;
+  if (H < 1 || W < 2 || (W & 1)) return FDL_ESHAPE;
+  const long long F = (long long)H * (W / 2 + 1);
+  if (F > (1LL << 30)) return FDL_ESHAPE;
+  fdl::ConstructParams P;
+  P.view_spec = reinterpret_cast<const float2*>(view_spec_dev);
+  P.u = nullptr;
+  P.views = nullptr;
+  P.shifts = reinterpret_cast<const float2*>(shifts_dev);
+  P.layer_spec = reinterpret_cast<float2*>(layer_spec_dev);
+  P.status = status_dev;
+  P.m = m; P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F;
+  P.lambda = (double)lambda; P.eps = (double)eps; P.reg = reg;
+  P.toeplitz = 0;
+  P.eta_max = 0.0;
+  for (int k = 0; k < 32; ++k) P.d[k] = 0.0;
+  trace("construct_relaxed m n C F", m, n, C, (int)F);
+  return map_hip(fdl::launch_construct_relaxed(P, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int fdl_render_relaxed(const fdl_c64* layer_spec_dev, const fdl_f2* shifts_dev, int n, int C, int H, int W, int V,
+                       fdl_c64* out_spec_dev, void* stream) {
+  if (!layer_spec_dev || !shifts_dev || !out_spec_dev) return FDL_EINVAL;
+  if (n < 1 || n > FDL_MAX_LAYERS || C < 1 || C > FDL_MAX_CHANNELS || V < 1) return FDL_ESHAPE;
+  if (H < 1 || W < 2 || (W & 1)) return FDL_ESHAPE;
+  const long long F = (long long)H * (W / 2 + 1);
+  if (F > (1LL << 30) || (F + 255) / 256 * ((V + 3) / 4) > 0x7fffffffLL) return FDL_ESHAPE;
+  fdl::RenderParams P;
+  P.layer_spec = reinterpret_cast<const float2*>(layer_spec_dev);
+  P.d = nullptr;
+  P.views = nullptr;
+  P.shifts = reinterpret_cast<const float2*>(shifts_dev);
+  P.out_spec = reinterpret_cast<float2*>(out_spec_dev);
+  P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F; P.V = V;
+  trace("render_relaxed n C F V", n, C, (int)F, V);
+  return map_hip(fdl::launch_render_relaxed(P, reinterpret_cast<hipStream_t>(stream)));
+}
+
+size_t fdl_calib_relaxed_workspace(int m, int n, int Q) {
+  if (m < 1 || n < 1 || Q < 1) return 0;
+  return (size_t)(Q < fdl::kCalibMaxBlocks ? Q : fdl::kCalibMaxBlocks) * (size_t)(1 + 2 * m * n) * sizeof(double);
+}
+
+int fdl_calib_grad_relaxed(const fdl_c64* view_spec_dev, const fdl_f2* shifts_dev, int m, int n, int C, int H, int W,
+                           float lambda, float eps, int reg, int mode, const int32_t* freq_idx_dev, int Q,
+                           double* loss_dev, double* grad_shifts_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+  if (!view_spec_dev || !shifts_dev || !loss_dev || !grad_shifts_dev || !ws_dev) return FDL_EINVAL;
+  if (!(std::isfinite(lambda) && lambda >= 0.f) || !(std::isfinite(eps) && eps >= 0.f)) return FDL_EINVAL;
+  if ((reg != FDL_REG_LAYER2 && reg != FDL_REG_L2) || (mode != FDL_LOSS_FIT && mode != FDL_LOSS_LOO))
+    return FDL_EINVAL;
+  if (m < 1 || m > 256 || n < 1 || n > FDL_MAX_LAYERS || C < 1 || C > FDL_MAX_CHANNELS) return FDL_ESHAPE;
+  if (H < 1 || W < 2 || (W & 1)) return FDL_ESHAPE;
+  const long long F = (long long)H * (W / 2 + 1);
+  if (F > (1LL << 30)) return FDL_ESHAPE;
+  if (!freq_idx_dev) Q = (int)F;
+  if (Q < 1) return FDL_EINVAL;
+  if (ws_bytes < fdl_calib_relaxed_workspace(m, n, Q)) return FDL_ENOMEM;
+  if (fdl::calib_lds_bytes(m, n, C, mode, true) > fdl::fft_lds_limit()) return FDL_ESHAPE;
+  fdl::CalibParams P;
+  P.view_spec = reinterpret_cast<const float2*>(view_spec_dev);
+  P.u = nullptr;
+  P.d = nullptr;
+  P.shifts = reinterpret_cast<const float2*>(shifts_dev);
+  P.freq_idx = freq_idx_dev;
+  P.partial = static_cast<double*>(ws_dev);
+  P.loss = loss_dev;
+  P.grad_u = nullptr;
+  P.grad_d = nullptr;
+  P.grad_p = grad_shifts_dev;
+  P.m = m; P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F; P.Q = Q;
+  P.lambda = (double)lambda; P.eps = (double)eps; P.bscale = 1.0 / std::sqrt((double)H * (double)W);
+  P.reg = reg; P.mode = mode; P.stride = 1 + 2 * m * n;
+  trace("calib_relaxed m n Q mode", m, n, Q, mode);
+  return map_hip(fdl::launch_calib(P, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int fdl_gd_step_relaxed(fdl_f2* shifts_dev, const double* grad_shifts_dev, int m, int n, double alpha, double eps_g,
+                        void* stream) {
+  if (!shifts_dev || !grad_shifts_dev) return FDL_EINVAL;
+  if (m < 1 || n < 1 || (long long)m * n > (1LL << 24) || !std::isfinite(alpha) || !(eps_g >= 0.0))
+    return FDL_EINVAL;
+  // the shift pairs are updated as one vector of m n positions; no disparities
+  return map_hip(fdl::launch_gd_step(reinterpret_cast<float2*>(shifts_dev), nullptr, grad_shifts_dev, nullptr, m * n,
+                                     0, alpha, eps_g, reinterpret_cast<hipStream_t>(stream)));
+}
+
 }  // extern "C"

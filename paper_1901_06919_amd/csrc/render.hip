@@ -7,6 +7,7 @@
 // view of the chunk accumulates in registers; the disk aperture spectrum
 // 2 J1(z)/z comes from a per-block LDS table of cubic pieces.  FP32
 // arithmetic: rendering is a plain weighted sum, no ill-conditioning.
+#include "fdl.h"
 #include "fdl_device.h"
 #include "fdl_internal.h"
 
@@ -218,6 +219,94 @@ hipError_t launch_render(const RenderParams& P, hipStream_t s) {
     case 2: return launch_render_vc<6, 2>(P, s);
     case 3: return launch_render_vc<4, 3>(P, s);
     default: return launch_render_vc<4, 4>(P, s);
+  }
+}
+
+// ---- relaxed model (Sec. VIII-B): the input views rendered with a free
+// shift pair per view and layer, B_j(w) = sum_k exp(2 pi i <P_jk, w>) L_k(w)
+// (the denoised output).  Same organisation as k_render: one thread per bin
+// and a chunk of VB views; the chunk's shifts sit in LDS and every thread of
+// the block reads the same entry (a broadcast).
+template <int VB, int CT>
+__global__ __launch_bounds__(256) void k_render_relaxed(RenderParams P, int nchunks) {
+  __shared__ float2 s_sh[VB][FDL_MAX_LAYERS];
+  const int b = xcd_remap(blockIdx.x, gridDim.x);
+  const int bin_block = b / nchunks;
+  const int v0 = (b - bin_block * nchunks) * VB;
+  const int nv = min(VB, P.V - v0);
+  const int n = P.n;
+  for (int i = threadIdx.x; i < VB * n; i += blockDim.x) {
+    const int v = i / n, k = i - v * n;
+    s_sh[v][k] = v < nv ? P.shifts[(size_t)(v0 + v) * n + k] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+
+  const int f = bin_block * 256 + threadIdx.x;
+  if (f >= P.F) return;
+  double wxd, wyd;
+  bin_freq(f, P.Wh, P.H, P.W, wxd, wyd);
+  const float wx = (float)wxd, wy = (float)wyd;
+  const int C = P.C;
+  const size_t F = (size_t)P.F;
+
+  float2 acc[VB][CT];
+#pragma unroll
+  for (int v = 0; v < VB; ++v)
+#pragma unroll
+    for (int c = 0; c < CT; ++c) acc[v][c] = make_float2(0.f, 0.f);
+
+  // layer k + 1 is loaded while layer k is processed (clamped, unconditional
+  // loads; channels c >= C repeat channel C - 1 and are never stored)
+  const float2* lp = P.layer_spec + f;
+  float2 xn[CT];
+  auto load_layer = [&](int k) {
+#pragma unroll
+    for (int c = 0; c < CT; ++c) xn[c] = lp[((size_t)k * C + (c < C ? c : C - 1)) * F];
+  };
+  load_layer(0);
+  for (int k = 0; k < n; ++k) {
+    float2 x[CT];
+#pragma unroll
+    for (int c = 0; c < CT; ++c) x[c] = xn[c];
+    load_layer(min(k + 1, n - 1));
+#pragma unroll
+    for (int v = 0; v < VB; ++v) {
+      if (v < nv) {
+        const float2 sh = s_sh[v][k];
+        float si, co;
+        sincos2pi_f(fmaf(sh.x, wx, sh.y * wy), si, co);
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          acc[v][c].x = fmaf(co, x[c].x, fmaf(-si, x[c].y, acc[v][c].x));
+          acc[v][c].y = fmaf(co, x[c].y, fmaf(si, x[c].x, acc[v][c].y));
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < VB; ++v) {
+    if (v < nv) {
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+        if (c < C) P.out_spec[((size_t)(v0 + v) * C + c) * F + f] = acc[v][c];
+    }
+  }
+}
+
+template <int VB, int CT>
+static hipError_t launch_render_relaxed_vc(const RenderParams& P, hipStream_t s) {
+  const int nchunks = (P.V + VB - 1) / VB;
+  const int bin_blocks = (P.F + 255) / 256;
+  hipLaunchKernelGGL((k_render_relaxed<VB, CT>), dim3(bin_blocks * nchunks), dim3(256), 0, s, P, nchunks);
+  return hipGetLastError();
+}
+
+hipError_t launch_render_relaxed(const RenderParams& P, hipStream_t s) {
+  switch (P.C) {
+    case 1: return launch_render_relaxed_vc<8, 1>(P, s);
+    case 2: return launch_render_relaxed_vc<6, 2>(P, s);
+    case 3: return launch_render_relaxed_vc<4, 3>(P, s);
+    default: return launch_render_relaxed_vc<4, 4>(P, s);
   }
 }
 

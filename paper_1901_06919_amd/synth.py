@@ -227,6 +227,16 @@ def config5(seed: int = 5, H: int = 256, W: int = 256):
     return spec, u0, d0
 
 
+def shift_deviations(m: int, n: int, rng: np.random.Generator, frac: float = 0.1, amp: float = 0.5) -> np.ndarray:
+    """Sparse departures from a rank-1 shift matrix, [m, n, 2] float32: a
+    fraction ``frac`` of the (view, layer) pairs moves by N(0, amp^2) pixels
+    per axis (a layer that some views see displaced, as an occlusion or a
+    non-Lambertian surface would make it); every other entry is 0."""
+    dev = (amp * rng.standard_normal((m, n, 2))).astype(np.float32)
+    keep = rng.random((m, n)) < frac
+    return dev * keep[:, :, None]
+
+
 @dataclasses.dataclass
 class Request:
     t_arrival: float      # seconds from stream start (scheduled arrival)

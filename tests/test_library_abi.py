@@ -53,3 +53,17 @@ def test_host_side_validation_without_gpu():
     assert L.fdl_fma64_probe(None, 1, 1, None) == -1
     assert L.fdl_construct_views(None, fake, d, 4, 4, 1, 8, 8, 0.01, 0.001, 0, fake, None, None) == -1
     assert L.fdl_construct_views(fake, fake, d, 4, 40, 1, 8, 8, 0.01, 0.001, 0, fake, None, None) == -2
+    # relaxed model: no view regulariser, shape limits, workspace size
+    assert L.fdl_construct_relaxed(fake, fake, 4, 4, 1, 8, 8, 0.01, 0.001, 0, fake, None, None) == -1
+    assert L.fdl_construct_relaxed(fake, None, 4, 4, 1, 8, 8, 0.01, 0.001, 1, fake, None, None) == -1
+    assert L.fdl_construct_relaxed(fake, fake, 4, 33, 1, 8, 8, 0.01, 0.001, 1, fake, None, None) == -2
+    assert L.fdl_render_relaxed(fake, fake, 33, 1, 8, 8, 1, fake, None) == -2
+    assert L.fdl_render_relaxed(fake, fake, 4, 1, 8, 8, 0, fake, None) == -2
+    assert L.fdl_calib_grad_relaxed(fake, fake, 4, 4, 1, 8, 8, 0.01, 0.001, 0, 0, None, 0,
+                                    fake, fake, fake, 1 << 20, None) == -1
+    assert L.fdl_calib_grad_relaxed(fake, fake, 300, 4, 1, 8, 8, 0.01, 0.001, 1, 0, None, 0,
+                                    fake, fake, fake, 1 << 20, None) == -2
+    assert L.fdl_calib_grad_relaxed(fake, fake, 4, 4, 1, 8, 8, 0.01, 0.001, 1, 0, None, 0,
+                                    fake, fake, fake, 16, None) == -3
+    assert L.fdl_calib_relaxed_workspace(49, 16, 4096) == 2048 * (1 + 2 * 49 * 16) * 8
+    assert L.fdl_gd_step_relaxed(None, fake, 4, 4, 0.2, 1e-6, None) == -1
