@@ -39,6 +39,16 @@ Readings of the paper used here (each stated where it is used):
       <P_jk, w>; grad P^x = sum_q G_jk w_x, grad P^y = sum_q G_jk w_y (Eq. gradP
       with both components); the update normalises by the squared norm over all
       2mn entries; the regulariser must not depend on d (LAYER2 or L2).
+* R6  drawn apertures (Sec. VI): an S x S image (S odd) tiles the box
+      [-1, 1]^2 of the aperture's own coordinates with cells of side 2/S,
+      pixel p centred at (p - (S-1)/2) 2/S (a symmetric grid), normalised to
+      unit sum; its spectrum is taken from the DFT of the image zero-padded
+      to N = pad S, i.e. at xi = k S / (2N) = k / (2 pad), k in [0, N) (the
+      samples are N-periodic because S - 1 is even), and read between samples
+      by bilinear interpolation with periodic wrap; a view's radius rho
+      scales the box, psi_hat_rho(xi) = psi_hat_1(rho xi), as the paper's
+      factor f does (a full image is the square of half-side rho, an
+      inscribed disk the disk of radius rho).
 """
 from __future__ import annotations
 
@@ -55,6 +65,7 @@ REG_L2 = 2
 AP_PINHOLE = 0
 AP_DISK = 1
 AP_SQUARE = 2
+AP_IMAGE = 3
 
 LOSS_FIT = 0
 LOSS_LOO = 1
@@ -561,6 +572,71 @@ def gd_step_relaxed(shifts: np.ndarray, grad: np.ndarray, alpha: float = 0.2, ep
     applied to the whole shift matrix (R5)."""
     g = np.asarray(grad, dtype=np.float64)
     return np.asarray(shifts, dtype=np.float64) - alpha * g / (eps_g + np.sum(g * g))
+
+
+# ---------------------------------------------------------------------------
+# Drawn apertures: the discrete aperture spectrum of Sec. VI (reading R6)
+# ---------------------------------------------------------------------------
+
+def aperture_table(img: np.ndarray, pad: int) -> np.ndarray:
+    """Spectrum samples of a drawn aperture, [N, N] complex128 (rows: k_y,
+    columns: k_x), N = pad S: the DFT of the unit-sum image zero-padded to
+    N x N (numpy.fft.fft2), times exp(+i pi (S-1)(k_x + k_y) / N), which moves
+    the origin from pixel 0 to the centre pixel (S-1)/2; entry k is psi_hat
+    at xi = k S / (2N)."""
+    a = np.asarray(img, dtype=np.float64)
+    S = a.shape[0]
+    if a.shape != (S, S) or S % 2 == 0:
+        raise ValueError("the aperture image must be S x S with S odd")
+    N = pad * S
+    w = np.zeros((N, N))
+    w[:S, :S] = a / a.sum()
+    X = np.fft.fft2(w)
+    k = np.arange(N)
+    ph = np.exp(1j * math.pi * (S - 1) * k / N)
+    return X * ph[:, None] * ph[None, :]
+
+
+def psi_hat_table(table: np.ndarray, S: int, rho: float, xi_x: np.ndarray, xi_y: np.ndarray) -> np.ndarray:
+    """psi_hat_rho(xi) = psi_hat_1(rho xi) read from :func:`aperture_table` by
+    bilinear interpolation in the continuous sample index t = rho xi 2N/S,
+    with periodic wrap of the sample grid (rho = 0 gives exactly 1)."""
+    N = table.shape[0]
+    tx = np.asarray(rho * np.asarray(xi_x, dtype=np.float64) * (2.0 * N / S))
+    ty = np.asarray(rho * np.asarray(xi_y, dtype=np.float64) * (2.0 * N / S))
+    x0 = np.floor(tx)
+    y0 = np.floor(ty)
+    fx = tx - x0
+    fy = ty - y0
+    ix = x0.astype(np.int64) % N
+    iy = y0.astype(np.int64) % N
+    ix1 = (ix + 1) % N
+    iy1 = (iy + 1) % N
+    return ((1 - fy) * ((1 - fx) * table[iy, ix] + fx * table[iy, ix1])
+            + fy * ((1 - fx) * table[iy1, ix] + fx * table[iy1, ix1]))
+
+
+def render_tabulated(layer_spec: np.ndarray, d: np.ndarray, views: np.ndarray, H: int, W: int,
+                     table: np.ndarray, S: int) -> np.ndarray:
+    """:func:`render` in which views of shape AP_IMAGE use the drawn aperture
+    whose spectrum is ``table`` (image size S), scaled by their radius."""
+    layer_spec = np.asarray(layer_spec)
+    n, C = layer_spec.shape[:2]
+    d = np.asarray(d, dtype=np.float64)
+    views = np.asarray(views, dtype=np.float64).reshape(-1, 5)
+    wx, wy = freq_grid(H, W)
+    out = np.zeros((views.shape[0], C) + wx.shape, dtype=np.complex128)
+    for v, (u0, v0, s, rho, shape) in enumerate(views):
+        acc = np.zeros((C,) + wx.shape, dtype=np.complex128)
+        for k in range(n):
+            phase = np.exp(2j * math.pi * d[k] * (u0 * wx + v0 * wy))
+            if int(round(shape)) == AP_IMAGE:
+                filt = psi_hat_table(table, S, rho, (s - d[k]) * wx, (s - d[k]) * wy)
+            else:
+                filt = psi_hat(int(round(shape)), rho, (s - d[k]) * wx, (s - d[k]) * wy)
+            acc += (phase * filt)[None, :, :] * layer_spec[k]
+        out[v] = acc
+    return out
 
 
 def rel_l2(y: np.ndarray, ref: np.ndarray) -> float:

@@ -536,3 +536,96 @@ def test_relaxed_gd_step_hand_values():
     P2 = O.gd_step_relaxed(np.array([[[1.0, 0.0]], [[0.0, 1.0]]]), np.array([[[2.0, 0.0]], [[0.0, 0.0]]]),
                            alpha=0.2, eps_g=0.0)
     np.testing.assert_allclose(P2, [[[0.9, 0.0]], [[0.0, 1.0]]])
+
+
+# ------------------------------------------------ drawn apertures (Sec. VI) ------
+
+def _drawn_disk(S):
+    c = (np.arange(S) - (S - 1) / 2) * (2.0 / S)
+    return ((c[None, :] ** 2 + c[:, None] ** 2) <= 1.0).astype(float)
+
+
+def test_aperture_table_matches_direct_sum():
+    """Every table entry is the Fourier sum of the unit-sum image over its
+    pixel centres (p - (S-1)/2) 2/S at xi = k S/(2N); the entry at k also
+    stands for k - N (periodic samples)."""
+    rng = np.random.default_rng(31)
+    S, pad = 5, 3
+    img = rng.uniform(0, 1, (S, S))
+    T = O.aperture_table(img, pad)
+    N = S * pad
+    w = img / img.sum()
+    c = (np.arange(S) - (S - 1) / 2) * (2.0 / S)
+    for ky in range(N):
+        for kx in range(N):
+            for sx, sy in ((0, 0), (-N, 0), (0, -N), (-N, -N)):
+                xx = (kx + sx) * S / (2 * N)
+                xy = (ky + sy) * S / (2 * N)
+                ref = sum(w[py, px] * cmath.exp(-2j * math.pi * (c[px] * xx + c[py] * xy))
+                          for py in range(S) for px in range(S))
+                assert abs(T[ky, kx] - ref) < 1e-12
+
+
+def test_table_interpolation_nodes_zero_radius_and_midpoints():
+    rng = np.random.default_rng(32)
+    S, pad = 7, 2
+    T = O.aperture_table(rng.uniform(0, 1, (S, S)), pad)
+    N = S * pad
+    step = S / (2 * N)                                   # xi between samples (rho = 1)
+    k = np.array([0, 3, 9, N - 1, -2])
+    got = O.psi_hat_table(T, S, 1.0, k * step, 2 * k * step)
+    np.testing.assert_allclose(got, T[(2 * k) % N, k % N], atol=1e-13)
+    assert np.all(O.psi_hat_table(T, S, 0.0, np.array([0.3, -2.0]), np.array([1.0, 0.5])) == T[0, 0])
+    assert abs(T[0, 0] - 1.0) < 1e-15
+    mid = O.psi_hat_table(T, S, 1.0, np.array([2.5 * step]), np.array([4.5 * step]))[0]
+    assert abs(mid - 0.25 * (T[4, 2] + T[4, 3] + T[5, 2] + T[5, 3])) < 1e-14
+
+
+def test_drawn_full_square_samples_are_the_dirichlet_kernel_near_the_sinc():
+    """A full image is a sampled square of half-side 1: its spectrum samples
+    are products of Dirichlet kernels sin(2 pi xi) / (S sin(2 pi xi / S))
+    (closed form of the geometric series), within (2 pi xi / S)^2 / 6 of the
+    analytic sinc(2 xi) of the square aperture."""
+    S, pad = 31, 4
+    T = O.aperture_table(np.ones((S, S)), pad)
+    N = S * pad
+    k = np.arange(-N // 2, N // 2)
+    xi = k * S / (2 * N)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        dk = np.where(k == 0, 1.0, np.sin(2 * math.pi * xi) / (S * np.sin(2 * math.pi * xi / S)))
+    np.testing.assert_allclose(T[0, k % N], dk, atol=1e-12)
+    np.testing.assert_allclose(T[k % N, 0], dk, atol=1e-12)
+    np.testing.assert_allclose(T[np.ix_(k % N, k % N)], np.outer(dk, dk), atol=1e-12)
+    small = np.abs(xi) <= 2.0
+    bound = (2 * math.pi * xi[small] / S) ** 2 / 6 + 1e-12
+    assert np.all(np.abs(dk[small] - np.sinc(2 * xi[small])) <= bound)
+
+
+def test_drawn_disk_render_approaches_the_analytic_disk():
+    """Rendering with an inscribed drawn disk converges to the analytic disk
+    aperture as the drawing gets finer and the padding larger."""
+    H, W = 16, 16
+    rng = np.random.default_rng(33)
+    layers = O.rfft2(rng.standard_normal((3, 1, H, W)))
+    d = np.array([-1.0, 0.0, 1.5])
+    views = np.array([[0.5, -0.5, 0.3, 1.2, O.AP_DISK], [0.0, 1.0, -0.8, 2.0, O.AP_DISK]])
+    ref = O.render(layers, d, views, H, W)
+    errs = []
+    for S, pad in ((15, 2), (63, 4), (127, 16)):
+        T = O.aperture_table(_drawn_disk(S), pad)
+        v = views.copy()
+        v[:, 4] = O.AP_IMAGE
+        errs.append(O.rel_l2(O.render_tabulated(layers, d, v, H, W, T, S), ref))
+    assert errs[0] > errs[1] > errs[2]
+    assert errs[2] < 3e-3
+
+
+def test_render_tabulated_without_image_views_is_render():
+    H, W = 12, 12
+    rng = np.random.default_rng(34)
+    layers = O.rfft2(rng.standard_normal((2, 2, H, W)))
+    d = np.array([-0.5, 1.0])
+    views = np.array([[0.5, 0.0, 0.3, 1.0, O.AP_DISK], [1.0, -1.0, 0.0, 0.7, O.AP_SQUARE], [0, 0, 0, 0, 0]])
+    T = O.aperture_table(np.ones((5, 5)), 2)
+    np.testing.assert_allclose(O.render_tabulated(layers, d, views, H, W, T, 5), O.render(layers, d, views, H, W),
+                               atol=1e-12)
