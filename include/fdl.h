@@ -78,7 +78,8 @@ enum fdl_loss {
 enum fdl_aperture {
   FDL_AP_PINHOLE = 0,     /* psi = delta, psi_hat = 1 */
   FDL_AP_DISK = 1,        /* unit-integral disk of radius rho: 2 J1(z)/z, z = 2 pi rho |xi| */
-  FDL_AP_SQUARE = 2       /* unit-integral square of half-side rho: sinc(2 rho xi_x) sinc(2 rho xi_y) */
+  FDL_AP_SQUARE = 2,      /* unit-integral square of half-side rho: sinc(2 rho xi_x) sinc(2 rho xi_y) */
+  FDL_AP_IMAGE = 3        /* drawn aperture scaled to half-side rho (fdl_render_tabulated); pinhole elsewhere */
 };
 
 /* Limits of this build. */
@@ -275,6 +276,33 @@ int fdl_batch_plan_autotune(fdl_batch_plan* plan, int reps, void* stream, float*
 int fdl_batch_plan_get_tuning(const fdl_batch_plan* plan, int32_t* mode, int32_t* chunk, int32_t* grid_per_cu);
 int fdl_batch_plan_set_tuning(fdl_batch_plan* plan, int32_t mode, int32_t chunk, int32_t grid_per_cu);
 int fdl_batch_plan_destroy(fdl_batch_plan* plan);
+
+/* ---------------------------------------------------------------------------
+ * Drawn apertures (Sec. VI: the aperture is drawn as an image, its spectrum
+ * taken from the DFT of the zero-padded image and read between the samples
+ * by linear interpolation; the view's radius plays the paper's scale f).
+ *
+ * fdl_aperture_table: img_dev [S][S] float32 on the device, S odd, 1 <= S <=
+ *   255; the image tiles the box [-1, 1]^2 of the aperture's own coordinates,
+ *   pixel (x, y) centred at ((x - (S-1)/2) 2/S, (y - (S-1)/2) 2/S); values are
+ *   weights (a 0/1 mask or grey levels, sum > 0; a zero sum gives non-finite
+ *   entries).  Writes table_dev [N][N] complex64, N = pad S <= 2048:
+ *     table[ky][kx] = psi_hat(kx S / (2N), ky S / (2N))
+ *                   = sum_{x,y} a[y][x] exp(-2 pi i <p_xy, xi>) / sum a,
+ *   samples that are N-periodic in kx and ky (FP64 sums, rounded to complex64).
+ * fdl_render_tabulated: fdl_render in which views of shape FDL_AP_IMAGE take
+ *   psi_hat_rho(xi) = psi_hat(rho xi) from the table (bilinear interpolation in
+ *   the sample index rho xi 2N/S, periodic wrap; complex in general), so a
+ *   full image renders as the square of half-side rho and an inscribed disk
+ *   as the disk of radius rho, up to the drawing and interpolation errors;
+ *   the other shapes are rendered as by fdl_render.  table_dev and (N, S) as
+ *   produced by fdl_aperture_table (N a multiple of S); other arguments and
+ *   errors as fdl_render.
+ * ------------------------------------------------------------------------- */
+int fdl_aperture_table(const float* img_dev, int S, int pad, fdl_c64* table_dev, void* stream);
+int fdl_render_tabulated(const fdl_c64* layer_spec_dev, const float* d_dev, int n, int C, int H, int W,
+                         const fdl_view* views_dev, int V, const fdl_c64* table_dev, int N, int S,
+                         fdl_c64* out_spec_dev, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Relaxed FDL model (Sec. VIII-B, denoising).  The shift of layer k in input

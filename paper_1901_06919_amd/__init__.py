@@ -26,6 +26,7 @@ LOSS_LOO = 1
 AP_PINHOLE = 0
 AP_DISK = 1
 AP_SQUARE = 2
+AP_IMAGE = 3
 MAX_LAYERS = 32
 MAX_CHANNELS = 4
 
@@ -91,6 +92,10 @@ def lib():
         L.fdl_batch_plan_set_tuning.argtypes = [vp, i32, i32, i32]
     L.fdl_fma64_probe.restype = i32
     L.fdl_fma64_probe.argtypes = [vp, i32, i32, vp]
+    L.fdl_aperture_table.restype = i32
+    L.fdl_aperture_table.argtypes = [vp, i32, i32, vp, vp]
+    L.fdl_render_tabulated.restype = i32
+    L.fdl_render_tabulated.argtypes = [vp, vp, i32, i32, i32, i32, vp, i32, vp, i32, i32, vp, vp]
     L.fdl_construct_relaxed.restype = i32
     L.fdl_construct_relaxed.argtypes = [vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, vp, vp, vp]
     L.fdl_render_relaxed.restype = i32
@@ -281,6 +286,43 @@ def gd_step(u: torch.Tensor, d: torch.Tensor, grad_u: torch.Tensor, grad_d: torc
     _check(grad_d, torch.float64, (n,), "grad_d")
     _call("fdl_gd_step", u.data_ptr(), d.data_ptr(), grad_u.data_ptr(), grad_d.data_ptr(), m, n,
           float(alpha), float(eps_g), _stream(u))
+
+
+# ---- drawn apertures (Sec. VI) ----
+
+def aperture_table(img: torch.Tensor, pad: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Spectrum samples [N, N] complex64, N = pad S, of a drawn aperture
+    img [S, S] float32 (S odd) on the device (fdl_aperture_table)."""
+    S = img.shape[0]
+    N = pad * S
+    _check(img, torch.float32, (S, S), "img")
+    if out is None:
+        out = torch.empty((N, N), dtype=torch.complex64, device=img.device)
+    _check(out, torch.complex64, (N, N), "out")
+    _call("fdl_aperture_table", img.data_ptr(), S, int(pad), out.data_ptr(), _stream(img))
+    return out
+
+
+def render_tabulated(layer_spec: torch.Tensor, d: torch.Tensor, views: torch.Tensor, H: int, W: int,
+                     table: torch.Tensor, S: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """:func:`render` in which views of shape AP_IMAGE use the drawn aperture
+    whose table (from :func:`aperture_table`, image side S) is given
+    (fdl_render_tabulated)."""
+    n, C = layer_spec.shape[:2]
+    _check(layer_spec, torch.complex64, (n, C, H, W // 2 + 1), "layer_spec")
+    _check(d, torch.float32, (n,), "d")
+    N = table.shape[0]
+    _check(table, torch.complex64, (N, N), "table")
+    if not views.is_cuda:
+        raise ValueError("views must be a device tensor")
+    rec = views if getattr(views, "_fdl_records", False) else view_records(views)
+    V = rec.shape[0]
+    if out is None:
+        out = torch.empty((V, C, H, W // 2 + 1), dtype=torch.complex64, device=layer_spec.device)
+    _check(out, torch.complex64, (V, C, H, W // 2 + 1), "out")
+    _call("fdl_render_tabulated", layer_spec.data_ptr(), d.data_ptr(), n, C, H, W, rec.data_ptr(), V,
+          table.data_ptr(), N, int(S), out.data_ptr(), _stream(layer_spec))
+    return out
 
 
 # ---- relaxed model (Sec. VIII-B): a free shift pair per view and layer ----

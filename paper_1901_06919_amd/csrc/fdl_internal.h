@@ -28,6 +28,9 @@ struct RenderParams {
   const float* d;            // [n]
   const void* views;         // [V] fdl_view (20 bytes each)
   const float2* shifts = nullptr;   // [V][n] shift pairs of the relaxed model (fdl_render_relaxed)
+  const float2* ap_tab = nullptr;   // [N][N] drawn-aperture spectrum samples (shape 3) or null
+  int ap_N = 0;
+  float ap_scale = 0.f;             // 2N / S: table index per unit of rho (s - d) w
   float2* out_spec;          // [V][C][F]
   int n, C, H, W, Wh, F, V;
 };
@@ -38,6 +41,9 @@ hipError_t launch_construct_views(const ConstructParams& P, hipStream_t s);   //
 hipError_t launch_construct_relaxed(const ConstructParams& P, hipStream_t s);   // free shifts per view and layer
 hipError_t launch_render(const RenderParams& P, hipStream_t s);
 hipError_t launch_render_relaxed(const RenderParams& P, hipStream_t s);
+constexpr int kApMaxS = 255;   // drawn aperture: image side (odd)
+constexpr int kApMaxN = 2048;  // and padded table side
+hipError_t launch_aperture_table(const float* img, int S, int N, float2* table, hipStream_t s);
 
 // Mixed-radix (4, 2, 3) plan for one FFT length.
 struct FftPlan {

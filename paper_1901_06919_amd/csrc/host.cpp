@@ -228,6 +228,39 @@ int fdl_gd_step(fdl_f2* u_dev, float* d_dev, const double* grad_u_dev, const dou
                                      eps_g, reinterpret_cast<hipStream_t>(stream)));
 }
 
+// ---- drawn apertures (Sec. VI) ----
+
+int fdl_aperture_table(const float* img_dev, int S, int pad, fdl_c64* table_dev, void* stream) {
+  if (!img_dev || !table_dev) return FDL_EINVAL;
+  if (S < 1 || S > fdl::kApMaxS || !(S & 1) || pad < 1 || (long long)pad * S > fdl::kApMaxN) return FDL_ESHAPE;
+  trace("aperture_table S N", S, pad * S, 0, 0);
+  return map_hip(fdl::launch_aperture_table(img_dev, S, pad * S, reinterpret_cast<float2*>(table_dev),
+                                            reinterpret_cast<hipStream_t>(stream)));
+}
+
+int fdl_render_tabulated(const fdl_c64* layer_spec_dev, const float* d_dev, int n, int C, int H, int W,
+                         const fdl_view* views_dev, int V, const fdl_c64* table_dev, int N, int S,
+                         fdl_c64* out_spec_dev, void* stream) {
+  if (!table_dev) return FDL_EINVAL;
+  if (S < 1 || S > fdl::kApMaxS || !(S & 1) || N < S || N > fdl::kApMaxN || N % S) return FDL_ESHAPE;
+  if (!layer_spec_dev || !d_dev || !views_dev || !out_spec_dev) return FDL_EINVAL;
+  if (n < 1 || n > FDL_MAX_LAYERS || C < 1 || C > FDL_MAX_CHANNELS || V < 1) return FDL_ESHAPE;
+  if (H < 1 || W < 2 || (W & 1)) return FDL_ESHAPE;
+  const long long F = (long long)H * (W / 2 + 1);
+  if (F > (1LL << 30) || (F + 255) / 256 * ((V + 3) / 4) > 0x7fffffffLL) return FDL_ESHAPE;
+  fdl::RenderParams P;
+  P.layer_spec = reinterpret_cast<const float2*>(layer_spec_dev);
+  P.d = d_dev;
+  P.views = views_dev;
+  P.out_spec = reinterpret_cast<float2*>(out_spec_dev);
+  P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F; P.V = V;
+  P.ap_tab = reinterpret_cast<const float2*>(table_dev);
+  P.ap_N = N;
+  P.ap_scale = (float)(2.0 * N / S);
+  trace("render_tabulated n C F V", n, C, (int)F, V);
+  return map_hip(fdl::launch_render(P, reinterpret_cast<hipStream_t>(stream)));
+}
+
 // ---- relaxed model (Sec. VIII-B): a free shift pair per view and layer ----
 
 int fdl_construct_relaxed(const fdl_c64* view_spec_dev, const fdl_f2* shifts_dev, int m, int n, int C, int H, int W,

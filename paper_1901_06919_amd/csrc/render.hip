@@ -103,7 +103,29 @@ __device__ __forceinline__ float jinc_tab(const float4* __restrict__ tab, float 
   return fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
 }
 
-template <int VB, int CT>
+// psi_hat of a drawn aperture from its table of spectrum samples (N x N,
+// rows k_y): bilinear interpolation at the continuous sample index (tx, ty),
+// periodic in both directions; indices are reduced in float and clamped, so
+// every read stays inside the table.
+__device__ __forceinline__ float2 aperture_tab(const float2* __restrict__ tab, int N, float tx, float ty) {
+  const float fN = (float)N;
+  const float x0 = floorf(tx), y0 = floorf(ty);
+  const float fx = tx - x0, fy = ty - y0;
+  int ix = (int)(x0 - fN * floorf(x0 / fN));
+  int iy = (int)(y0 - fN * floorf(y0 / fN));
+  ix = min(max(ix, 0), N - 1);
+  iy = min(max(iy, 0), N - 1);
+  const int ix1 = ix + 1 == N ? 0 : ix + 1;
+  const int iy1 = iy + 1 == N ? 0 : iy + 1;
+  const float2 a = tab[(size_t)iy * N + ix], b = tab[(size_t)iy * N + ix1];
+  const float2 c = tab[(size_t)iy1 * N + ix], e = tab[(size_t)iy1 * N + ix1];
+  const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy), w10 = (1.f - fx) * fy, w11 = fx * fy;
+  return make_float2(w00 * a.x + w01 * b.x + w10 * c.x + w11 * e.x, w00 * a.y + w01 * b.y + w10 * c.y + w11 * e.y);
+}
+
+// TAB: views of shape 3 take their aperture spectrum from the drawn-aperture
+// table (complex in general); without it shape 3 renders as a pinhole.
+template <int VB, int CT, bool TAB = false>
 __global__ __launch_bounds__(256) void k_render(RenderParams P, int nchunks) {
   __shared__ ViewRec s_v[VB];
   __shared__ float4 s_jinc[kJincN];
@@ -138,11 +160,16 @@ __global__ __launch_bounds__(256) void k_render(RenderParams P, int nchunks) {
     const int shape = __builtin_amdgcn_readfirstlane(rv.shape);
     const bool open = __builtin_amdgcn_readfirstlane(__float_as_int(rv.radius)) != 0 &&
                       __builtin_amdgcn_readfirstlane(__float_as_int(rv.radius)) != (int)0x80000000;
-    kind[v] = open && (shape == 1 || shape == 2) ? shape : 0;
+    kind[v] = open && (shape == 1 || shape == 2 || (TAB && shape == 3)) ? shape : 0;
     pv[v] = rv.u * wx + rv.v * wy;
     sv[v] = rv.focus;
-    g1[v] = rv.shape == 1 ? (float)kTwoPi * rv.radius * wn : 2.0f * rv.radius * wx;
-    g2[v] = 2.0f * rv.radius * wy;
+    if (TAB && shape == 3) {   // continuous table index per unit of (s - d)
+      g1[v] = rv.radius * wx * P.ap_scale;
+      g2[v] = rv.radius * wy * P.ap_scale;
+    } else {
+      g1[v] = rv.shape == 1 ? (float)kTwoPi * rv.radius * wn : 2.0f * rv.radius * wx;
+      g2[v] = 2.0f * rv.radius * wy;
+    }
   }
 
   float2 acc[VB][CT];
@@ -181,9 +208,17 @@ __global__ __launch_bounds__(256) void k_render(RenderParams P, int nchunks) {
         sincos2pi_f(dk * pv[v], s, co);
         const float a = sv[v] - dk;
         float g = 1.0f;
-        if (kind[v] == 1) g = jinc_tab(s_jinc, g1[v] * fabsf(a));
-        else if (kind[v] == 2) g = sinc_fast(g1[v] * a) * sinc_fast(g2[v] * a);
-        const float pr = co * g, pi = s * g;
+        float pr, pi;
+        if (TAB && kind[v] == 3) {
+          const float2 q = aperture_tab(P.ap_tab, P.ap_N, g1[v] * a, g2[v] * a);
+          pr = co * q.x - s * q.y;
+          pi = s * q.x + co * q.y;
+        } else {
+          if (kind[v] == 1) g = jinc_tab(s_jinc, g1[v] * fabsf(a));
+          else if (kind[v] == 2) g = sinc_fast(g1[v] * a) * sinc_fast(g2[v] * a);
+          pr = co * g;
+          pi = s * g;
+        }
 #pragma unroll
         for (int c = 0; c < CT; ++c) {
           acc[v][c].x = fmaf(pr, x[c].x, fmaf(-pi, x[c].y, acc[v][c].x));
@@ -206,7 +241,10 @@ template <int VB, int CT>
 static hipError_t launch_render_vc(const RenderParams& P, hipStream_t s) {
   const int nchunks = (P.V + VB - 1) / VB;
   const int bin_blocks = (P.F + 255) / 256;
-  hipLaunchKernelGGL((k_render<VB, CT>), dim3(bin_blocks * nchunks), dim3(256), 0, s, P, nchunks);
+  if (P.ap_tab)
+    hipLaunchKernelGGL((k_render<VB, CT, true>), dim3(bin_blocks * nchunks), dim3(256), 0, s, P, nchunks);
+  else
+    hipLaunchKernelGGL((k_render<VB, CT>), dim3(bin_blocks * nchunks), dim3(256), 0, s, P, nchunks);
   return hipGetLastError();
 }
 
@@ -220,6 +258,66 @@ hipError_t launch_render(const RenderParams& P, hipStream_t s) {
     case 3: return launch_render_vc<4, 3>(P, s);
     default: return launch_render_vc<4, 4>(P, s);
   }
+}
+
+// ---- drawn apertures (Sec. VI): spectrum samples of an aperture image ----
+// table[ky][kx] = sum_{y,x} a[y][x] exp(-2 pi i (x kx + y ky) / N)
+//                 * exp(+i pi (S - 1)(kx + ky) / N) / sum a,
+// the DFT of the unit-sum S x S image zero-padded to N x N with the origin
+// moved to the centre pixel.  One block per table row ky: the column sums
+// c[x] = sum_y a[y][x] exp(-2 pi i y ky / N) go to LDS (FP64), then every
+// thread finishes entries kx with a table of exp(-2 pi i r / N).
+__global__ __launch_bounds__(256) void k_aperture_table(const float* __restrict__ img, int S, int N,
+                                                        float2* __restrict__ table) {
+  __shared__ double2 s_ph[kApMaxN];      // exp(-2 pi i r / N), r < N
+  __shared__ double2 s_col[kApMaxS];
+  __shared__ double s_sum[256];
+  const int ky = blockIdx.x;
+  const int t = threadIdx.x;
+  for (int r = t; r < N; r += 256) {
+    double sn, cs;
+    sincospi(-2.0 * (double)r / (double)N, &sn, &cs);
+    s_ph[r] = make_double2(cs, sn);
+  }
+  __syncthreads();
+  double part = 0.0;
+  for (int x = t; x < S; x += 256) {
+    double re = 0.0, im = 0.0;
+    for (int y = 0; y < S; ++y) {
+      const double a = (double)img[(size_t)y * S + x];
+      const double2 e = s_ph[(int)(((long long)y * ky) % N)];
+      re = fma(a, e.x, re);
+      im = fma(a, e.y, im);
+      part += a;
+    }
+    s_col[x] = make_double2(re, im);
+  }
+  s_sum[t] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) s_sum[t] += s_sum[t + w];
+    __syncthreads();
+  }
+  const double inv = 1.0 / s_sum[0];
+  for (int kx = t; kx < N; kx += 256) {
+    double re = 0.0, im = 0.0;
+    for (int x = 0; x < S; ++x) {
+      const double2 c = s_col[x];
+      const double2 e = s_ph[(int)(((long long)x * kx) % N)];
+      re += c.x * e.x - c.y * e.y;
+      im += c.x * e.y + c.y * e.x;
+    }
+    // exp(+i pi (S - 1)(kx + ky) / N) = conj of the table entry at (S - 1)(kx + ky) / 2 mod N
+    const long long q = ((long long)(S - 1) / 2 * (long long)(kx + ky)) % N;
+    const double2 e = s_ph[(int)q];
+    const double pr = re * e.x + im * e.y, pi = im * e.x - re * e.y;
+    table[(size_t)ky * N + kx] = make_float2((float)(pr * inv), (float)(pi * inv));
+  }
+}
+
+hipError_t launch_aperture_table(const float* img, int S, int N, float2* table, hipStream_t s) {
+  hipLaunchKernelGGL(k_aperture_table, dim3(N), dim3(256), 0, s, img, S, N, table);
+  return hipGetLastError();
 }
 
 // ---- relaxed model (Sec. VIII-B): the input views rendered with a free

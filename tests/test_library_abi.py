@@ -67,3 +67,9 @@ def test_host_side_validation_without_gpu():
                                     fake, fake, fake, 16, None) == -3
     assert L.fdl_calib_relaxed_workspace(49, 16, 4096) == 2048 * (1 + 2 * 49 * 16) * 8
     assert L.fdl_gd_step_relaxed(None, fake, 4, 4, 0.2, 1e-6, None) == -1
+    # drawn apertures: odd image side, table size limits
+    assert L.fdl_aperture_table(fake, 4, 2, fake, None) == -2
+    assert L.fdl_aperture_table(fake, 255, 9, fake, None) == -2
+    assert L.fdl_aperture_table(None, 5, 2, fake, None) == -1
+    assert L.fdl_render_tabulated(fake, fake, 4, 1, 8, 8, fake, 1, fake, 12, 5, fake, None) == -2
+    assert L.fdl_render_tabulated(fake, fake, 4, 1, 8, 8, fake, 1, None, 10, 5, fake, None) == -1
