@@ -39,6 +39,12 @@ Readings of the paper used here (each stated where it is used):
       <P_jk, w>; grad P^x = sum_q G_jk w_x, grad P^y = sum_q G_jk w_y (Eq. gradP
       with both components); the update normalises by the squared norm over all
       2mn entries; the regulariser must not depend on d (LAYER2 or L2).
+* R7  second-order view regulariser over a finite camera-plane region
+      (Eq. GTG): in 2D the region is the square [-r/2, r/2]^2 and the
+      derivative functional is |w|^2 d_k^2 exp(2 pi i d_k <u, w>) (reading R2),
+      so after division by the area r^2 the matrix is
+      |w|^4 d_k1^2 d_k2^2 sinc(r (d_k1 - d_k2) w_x) sinc(r (d_k1 - d_k2) w_y),
+      whose r -> infinity limit is the diagonal of REG_VIEW2.
 * R6  drawn apertures (Sec. VI): an S x S image (S odd) tiles the box
       [-1, 1]^2 of the aperture's own coordinates with cells of side 2/S,
       pixel p centred at (p - (S-1)/2) 2/S (a symmetric grid), normalised to
@@ -61,6 +67,7 @@ from scipy.special import j1 as _bessel_j1
 REG_VIEW2 = 0
 REG_LAYER2 = 1
 REG_L2 = 2
+REG_VIEW2_REGION = 3
 
 AP_PINHOLE = 0
 AP_DISK = 1
@@ -124,13 +131,15 @@ def second_difference(n: int) -> np.ndarray:
     return G
 
 
-def reg_matrix(reg: int, d: np.ndarray, wx: np.ndarray, wy: np.ndarray) -> np.ndarray:
+def reg_matrix(reg: int, d: np.ndarray, wx: np.ndarray, wy: np.ndarray, r: Optional[float] = None) -> np.ndarray:
     """Gamma^H Gamma per frequency, [F, n, n] (real).
 
     REG_VIEW2:  diag(|w|^4 d_k^4)  -- Eq. 2ndOrderView, the r -> infinity limit
                 of Eq. GTG, with w^4 read as (w_x^2 + w_y^2)^2 in 2D (R2).
     REG_LAYER2: Gamma^T Gamma with Gamma = tridiag(1,-2,1) (Eq. 2ndOrderLayer).
     REG_L2:     identity (Sec. V-C, classical l2).
+    REG_VIEW2_REGION: Eq. GTG over the camera-plane square of side r, divided
+                by its area (R7); dense, real, positive semi-definite.
     """
     d = np.asarray(d, dtype=np.float64)
     n = d.shape[0]
@@ -146,6 +155,15 @@ def reg_matrix(reg: int, d: np.ndarray, wx: np.ndarray, wy: np.ndarray) -> np.nd
         return np.broadcast_to(G.T @ G, (F, n, n)).copy()
     if reg == REG_L2:
         return np.broadcast_to(np.eye(n), (F, n, n)).copy()
+    if reg == REG_VIEW2_REGION:
+        # Eq. GTG divided by the region's area (R7); r is the side of the region
+        if r is None or not r > 0:
+            raise ValueError("REG_VIEW2_REGION needs the region side r > 0")
+        w4 = (wx * wx + wy * wy) ** 2
+        dd = d[:, None] - d[None, :]                                       # [n, n]
+        sx = np.sinc(r * dd[None] * wx[:, None, None])
+        sy = np.sinc(r * dd[None] * wy[:, None, None])
+        return w4[:, None, None] * (d * d)[None, :, None] * (d * d)[None, None, :] * sx * sy
     raise ValueError(f"unknown regulariser {reg}")
 
 
@@ -163,7 +181,8 @@ def normal_matrix(A: np.ndarray, R: np.ndarray, lam: float, eps: float) -> np.nd
 
 def construct(view_spec: np.ndarray, u: np.ndarray, d: np.ndarray, H: int, W: int,
               lam: float, eps: float, reg: int = REG_VIEW2,
-              freq_index: Optional[np.ndarray] = None, chunk: int = 2048) -> np.ndarray:
+              freq_index: Optional[np.ndarray] = None, chunk: int = 2048,
+              region: Optional[float] = None) -> np.ndarray:
     """Closed-form Tikhonov solution x(w) = (A^H A + lam G + eps I)^-1 A^H b(w)
     at every half-spectrum bin, independently per bin and shared across colour
     channels.
@@ -171,6 +190,7 @@ def construct(view_spec: np.ndarray, u: np.ndarray, d: np.ndarray, H: int, W: in
     view_spec: [m, C, H, W//2+1] complex spectra of the input views.
     Returns layer spectra [n, C, H, W//2+1] complex128, or, when
     ``freq_index`` (flat bin indices) is given, [n, C, len(freq_index)].
+    ``region`` is the side r of the camera-plane square of REG_VIEW2_REGION.
     """
     view_spec = np.asarray(view_spec)
     m, C = view_spec.shape[:2]
@@ -185,7 +205,7 @@ def construct(view_spec: np.ndarray, u: np.ndarray, d: np.ndarray, H: int, W: in
         fi = freq_index[s:s + chunk]
         wx, wy = wx_all[fi], wy_all[fi]
         A = a_matrix(u, d, wx, wy)                                         # [F, m, n]
-        M = normal_matrix(A, reg_matrix(reg, d, wx, wy), lam, eps)         # [F, n, n]
+        M = normal_matrix(A, reg_matrix(reg, d, wx, wy, region), lam, eps)  # [F, n, n]
         b = np.transpose(b_all[:, :, fi], (2, 0, 1)).astype(np.complex128)  # [F, m, C]
         c = np.conj(np.swapaxes(A, -1, -2)) @ b                           # [F, n, C]
         x = np.linalg.solve(M, c)                                          # [F, n, C]

@@ -629,3 +629,67 @@ def test_render_tabulated_without_image_views_is_render():
     T = O.aperture_table(np.ones((5, 5)), 2)
     np.testing.assert_allclose(O.render_tabulated(layers, d, views, H, W, T, 5), O.render(layers, d, views, H, W),
                                atol=1e-12)
+
+
+# ------------------------------------- finite-region view regulariser (Eq. GTG) ------
+
+def test_region_regulariser_matches_quadrature_of_its_integral():
+    """Eq. GTG written as an integral over the square [-r/2, r/2]^2 of
+    Gamma_k1(u) conj(Gamma_k2(u)), Gamma_k(u) = |w|^2 d_k^2 exp(2 pi i d_k <u, w>),
+    divided by r^2, by the midpoint rule on a fine grid."""
+    d = np.array([-1.3, -0.2, 0.4, 1.7])
+    wx = np.array([0.11, -0.31, 0.05])
+    wy = np.array([-0.07, 0.22, 0.0])
+    r = 3.0
+    R = O.reg_matrix(O.REG_VIEW2_REGION, d, wx, wy, r)
+    N = 400
+    t = (np.arange(N) + 0.5) / N * r - r / 2
+    uu, vv = np.meshgrid(t, t, indexing="xy")
+    for f in range(3):
+        w2 = wx[f] ** 2 + wy[f] ** 2
+        G = np.stack([w2 * dk ** 2 * np.exp(2j * math.pi * dk * (uu * wx[f] + vv * wy[f])) for dk in d])
+        Q = np.einsum("kab,lab->kl", G, np.conj(G)) * (r / N) ** 2 / r ** 2
+        np.testing.assert_allclose(R[f], Q, rtol=0, atol=1e-5 * np.abs(Q).max())
+
+
+def test_region_regulariser_tends_to_the_view_regulariser():
+    """r -> infinity: the off-diagonal sinc products vanish (as 1/(pi r dd w)^2
+    at most) and the diagonal is diag(|w|^4 d^4) for every r."""
+    rng = np.random.default_rng(35)
+    d = np.sort(rng.uniform(-2, 2, 6))
+    wx = rng.uniform(-0.5, 0.5, 10)
+    wy = rng.uniform(-0.5, 0.5, 10)
+    V = O.reg_matrix(O.REG_VIEW2, d, wx, wy)
+    for r in (10.0, 1e3, 1e5):
+        R = O.reg_matrix(O.REG_VIEW2_REGION, d, wx, wy, r)
+        idx = np.arange(6)
+        np.testing.assert_allclose(R[:, idx, idx], V[:, idx, idx], rtol=1e-14)
+        dd = np.abs(d[:, None] - d[None, :]) + np.eye(6)
+        bound = 1.0 / (math.pi * r * dd[None] * np.abs(wx)[:, None, None]) / (math.pi * r * dd[None] *
+                                                                              np.abs(wy)[:, None, None])
+        off = np.abs(R - V)
+        assert np.all(off <= bound * np.abs(V).max() + 1e-300)
+
+
+def test_region_regulariser_is_positive_semidefinite_and_construct_uses_it():
+    rng = np.random.default_rng(36)
+    d = np.sort(rng.uniform(-2, 2, 7))
+    wx = rng.uniform(-0.5, 0.5, 20)
+    wy = rng.uniform(-0.5, 0.5, 20)
+    R = O.reg_matrix(O.REG_VIEW2_REGION, d, wx, wy, 2.5)
+    ev = np.linalg.eigvalsh(R)
+    assert ev.min() >= -1e-12 * ev.max()
+    H, W = 8, 8
+    u, d2, spec = _tiny_problem(5, H=H, W=W)
+    lam, eps = 0.4, 1e-2
+    x = O.construct(spec, u, d2, H, W, lam, eps, O.REG_VIEW2_REGION, region=2.0)
+    wgx, wgy = O.freq_grid(H, W)
+    for ky in range(H):
+        for kx in range(W // 2 + 1):
+            A = _explicit_A(u, d2, wgx[ky, kx], wgy[ky, kx])
+            Rk = O.reg_matrix(O.REG_VIEW2_REGION, d2, np.array([wgx[ky, kx]]), np.array([wgy[ky, kx]]), 2.0)[0]
+            # a square root of the (semi-definite) regulariser as the stacked rows
+            lam_k, U = np.linalg.eigh(Rk)
+            Gam = (U * np.sqrt(np.clip(lam_k, 0, None))).T
+            ref = brute.stacked_lstsq(A, spec[:, :, ky, kx], Gam, lam, eps)
+            np.testing.assert_allclose(x[:, :, ky, kx], ref, rtol=1e-8, atol=1e-9)
