@@ -278,6 +278,20 @@ int fdl_batch_plan_set_tuning(fdl_batch_plan* plan, int32_t mode, int32_t chunk,
 int fdl_batch_plan_destroy(fdl_batch_plan* plan);
 
 /* ---------------------------------------------------------------------------
+ * Layer construction with the second-order view regulariser restricted to a
+ * finite square [-r/2, r/2]^2 of the camera plane (Eq. GTG, divided by the
+ * area r^2, in 2D): as fdl_construct, with R(w) the dense real matrix
+ *   R_k1k2 = |w|^4 d_k1^2 d_k2^2 sinc(r (d_k1 - d_k2) w_x) sinc(r (d_k1 - d_k2) w_y),
+ * sinc(t) = sin(pi t)/(pi t); r -> infinity gives FDL_REG_VIEW2.  region = r
+ * (finite, > 0; FDL_EINVAL otherwise).  The off-diagonal entries use the FP32
+ * sine (about 1e-7 relative); all other arguments, layouts, status and
+ * errors as fdl_construct.
+ * ------------------------------------------------------------------------- */
+int fdl_construct_region(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_host, int m, int n, int C,
+                         int H, int W, float lambda, float eps, float region, fdl_c64* layer_spec_dev,
+                         int32_t* status_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Drawn apertures (Sec. VI: the aperture is drawn as an image, its spectrum
  * taken from the DFT of the zero-padded image and read between the samples
  * by linear interpolation; the view's radius plays the paper's scale f).

@@ -92,6 +92,8 @@ def lib():
         L.fdl_batch_plan_set_tuning.argtypes = [vp, i32, i32, i32]
     L.fdl_fma64_probe.restype = i32
     L.fdl_fma64_probe.argtypes = [vp, i32, i32, vp]
+    L.fdl_construct_region.restype = i32
+    L.fdl_construct_region.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, f32, vp, vp, vp]
     L.fdl_aperture_table.restype = i32
     L.fdl_aperture_table.argtypes = [vp, i32, i32, vp, vp]
     L.fdl_render_tabulated.restype = i32
@@ -286,6 +288,30 @@ def gd_step(u: torch.Tensor, d: torch.Tensor, grad_u: torch.Tensor, grad_d: torc
     _check(grad_d, torch.float64, (n,), "grad_d")
     _call("fdl_gd_step", u.data_ptr(), d.data_ptr(), grad_u.data_ptr(), grad_d.data_ptr(), m, n,
           float(alpha), float(eps_g), _stream(u))
+
+
+def construct_region(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int, W: int, lam: float,
+                     eps: float, region: float, out: Optional[torch.Tensor] = None,
+                     status: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Layer spectra with the view regulariser over the camera-plane square of
+    side ``region`` (fdl_construct_region); otherwise as :func:`construct`."""
+    m, C = view_spec.shape[:2]
+    n = d.shape[0]
+    _check(view_spec, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
+    _check(u, torch.float32, (m, 2), "u")
+    if d.dtype != torch.float32 or d.dim() != 1:
+        raise TypeError("d must be a 1-D float32 tensor")
+    d_host = d.detach().to("cpu").contiguous()
+    if out is None:
+        out = torch.empty((n, C, H, W // 2 + 1), dtype=torch.complex64, device=view_spec.device)
+    _check(out, torch.complex64, (n, C, H, W // 2 + 1), "out")
+    sp = 0
+    if status is not None:
+        _check(status, torch.int32, (1,), "status")
+        sp = status.data_ptr()
+    _call("fdl_construct_region", view_spec.data_ptr(), u.data_ptr(), d_host.data_ptr(), m, n, C, H, W,
+          float(lam), float(eps), float(region), out.data_ptr(), sp, _stream(view_spec))
+    return out
 
 
 # ---- drawn apertures (Sec. VI) ----

@@ -107,6 +107,17 @@ __device__ __forceinline__ double aperture64(int shape, double rho, double a, do
   return 1.0;
 }
 
+// sin(pi x) / (pi x) for the regulariser entries: exact reduction of the
+// half-angle in FP64, then the FP32 transcendental unit (about 1e-7).
+__device__ __forceinline__ float sinc_pi(double x) {
+  if (fabs(x) < 1e-4) {
+    const double a = kPi * x;
+    return (float)(1.0 - a * a * (1.0 / 6.0));
+  }
+  const double h = 0.5 * x;
+  return __builtin_amdgcn_sinf((float)(h - rint(h))) / (float)(kPi * x);
+}
+
 // Per-block table of exp(2 pi i t / kPhaseTab), t = 0..kPhaseTab-1.
 constexpr int kPhaseTab = 256;
 
@@ -222,7 +233,11 @@ __device__ __forceinline__ void team_transpose(TeamRows<R>& S, double2* tr, int 
 // A_jk = exp(2 pi i d_k p_j) psi_hat_j((s_j - d_k) w), general Gram path only.
 // SHIFTS: the relaxed model (Sec. VIII-B), a free shift pair per view and
 // layer: A_jk = exp(2 pi i <P_jk, w>), general Gram path only.
-template <int R, int CT, bool TOEP, bool APER = false, bool SHIFTS = false>
+// REGION: the second-order view regulariser over the camera-plane square of
+// side P.region (Eq. GTG): the diagonal of the view regulariser plus the dense
+// off-diagonal part lambda |w|^4 d_i^2 d_k^2 sinc(r dd w_x) sinc(r dd w_y)
+// (P.reg must be 0).
+template <int R, int CT, bool TOEP, bool APER = false, bool SHIFTS = false, bool REGION = false>
 __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>& T, const double2* __restrict__ tab,
                                            int f, int lane) {
   static_assert(!(TOEP && APER), "apertures break the Toeplitz structure");
@@ -483,6 +498,28 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
         pin(e);
         S.template at<r>(k) = e;
       });
+    });
+  }
+
+  if constexpr (REGION) {
+    // dense part of the finite-region view regulariser (the diagonal is the
+    // one of the view regulariser, already in place); padded rows untouched
+    sched_fence();
+    const double w2 = wx * wx + wy * wy;
+    const double lw = P.lambda * w2 * w2;
+    const double rx = P.region * wx, ry = P.region * wy;
+    static_for<0, R>([&](auto RR) {
+      constexpr int r = decltype(RR)::value;
+      const int i = lane + 16 * r;
+      const double ci = lw * dk[r] * dk[r];
+      static_for<0, 16 * (r + 1)>([&](auto KK) {
+        constexpr int k = decltype(KK)::value;
+        const double dkk = T.m.d[k];
+        const double dd = dk[r] - dkk;
+        const double g = ci * dkk * dkk * (double)(sinc_pi(rx * dd) * sinc_pi(ry * dd));
+        S.template at<r>(k).re += (k < i && i < n) ? g : 0.0;
+      });
+      sched_fence();
     });
   }
 

@@ -20,6 +20,7 @@ struct ConstructParams {
   int reg;
   int toeplitz;              // 1: d is an arithmetic progression up to rounding
   double eta_max;            // max_k1<k2 |(d_k2-d_k1) - (d_{k2-k1}-d_0)|
+  double region = 0.0;       // side of the camera-plane square of the finite-region regulariser
   double d[32];
 };
 
@@ -39,6 +40,7 @@ hipError_t launch_construct_r1(const ConstructParams& P, hipStream_t s);   // n 
 hipError_t launch_construct_r2(const ConstructParams& P, hipStream_t s);   // n <= 32
 hipError_t launch_construct_views(const ConstructParams& P, hipStream_t s);   // inputs with apertures
 hipError_t launch_construct_relaxed(const ConstructParams& P, hipStream_t s);   // free shifts per view and layer
+hipError_t launch_construct_region(const ConstructParams& P, hipStream_t s);    // finite-region view regulariser
 hipError_t launch_render(const RenderParams& P, hipStream_t s);
 hipError_t launch_render_relaxed(const RenderParams& P, hipStream_t s);
 constexpr int kApMaxS = 255;   // drawn aperture: image side (odd)

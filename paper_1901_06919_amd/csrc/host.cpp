@@ -228,6 +228,35 @@ int fdl_gd_step(fdl_f2* u_dev, float* d_dev, const double* grad_u_dev, const dou
                                      eps_g, reinterpret_cast<hipStream_t>(stream)));
 }
 
+// ---- finite-region view regulariser (Eq. GTG) ----
+
+int fdl_construct_region(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_host, int m, int n, int C,
+                         int H, int W, float lambda, float eps, float region, fdl_c64* layer_spec_dev,
+                         int32_t* status_dev, void* stream) {
+  if (!view_spec_dev || !u_dev || !d_host || !layer_spec_dev) return FDL_EINVAL;
+  if (!(std::isfinite(lambda) && lambda >= 0.f) || !(std::isfinite(eps) && eps >= 0.f)) return FDL_EINVAL;
+  if (!(std::isfinite(region) && region > 0.f)) return FDL_EINVAL;
+  if (m < 1 || m > 4096 || n < 1 || n > FDL_MAX_LAYERS || C < 1 || C > FDL_MAX_CHANNELS) return FDL_ESHAPE;
+  if (H < 1 || W < 2 || (W & 1)) return FDL_ESHAPE;
+  for (int k = 0; k < n; ++k)
+    if (!std::isfinite(d_host[k])) return FDL_EINVAL;
+  const long long F = (long long)H * (W / 2 + 1);
+  if (F > (1LL << 30)) return FDL_ESHAPE;
+  fdl::ConstructParams P;
+  P.view_spec = reinterpret_cast<const float2*>(view_spec_dev);
+  P.u = reinterpret_cast<const float2*>(u_dev);
+  P.views = nullptr;
+  P.layer_spec = reinterpret_cast<float2*>(layer_spec_dev);
+  P.status = status_dev;
+  P.m = m; P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F;
+  P.lambda = (double)lambda; P.eps = (double)eps;
+  P.reg = FDL_REG_VIEW2;          // diagonal of the view regulariser; the dense part is added on top
+  P.region = (double)region;
+  fdl_host::classify(d_host, n, P);
+  trace("construct_region m n C F", m, n, C, (int)F);
+  return map_hip(fdl::launch_construct_region(P, reinterpret_cast<hipStream_t>(stream)));
+}
+
 // ---- drawn apertures (Sec. VI) ----
 
 int fdl_aperture_table(const float* img_dev, int S, int pad, fdl_c64* table_dev, void* stream) {
