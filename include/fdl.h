@@ -204,9 +204,9 @@ int fdl_construct_views(const fdl_c64* view_spec_dev, const fdl_view* views_dev,
  * Q >= 1 when freq_idx_dev != NULL, every index in [0, F) (not checked: an
  * index outside [0, F) reads outside view_spec_dev), and the per-bin system
  * must fit the LDS one block may use on the device (160 KiB on MI355X):
- * 8 * (2mn + 2n^2 + 4mC + 2nC + m + mn + 256) bytes for FIT, plus
- * 8 * (2nm + 4mC + 2nC + m + 2n^2) for LOO (FDL_ESHAPE otherwise; m = 49,
- * n = 16, C = 1 needs 46 KiB in LOO mode, m = 81, n = 30, C = 3 FIT 85 KiB).
+ * 8 * max(2mn + 2n^2 + n + 4mC + 2nC + m + mn, 256) bytes for FIT, plus
+ * 8 * (2nm + 4mC + 2nC + m) for LOO (FDL_ESHAPE otherwise; m = 49, n = 16,
+ * C = 1 needs 39 KiB in LOO mode, m = 81, n = 30, C = 3 FIT 81 KiB).
  * With FDL_REG_VIEW2 the regulariser depends on d; its derivative is not
  * included (the paper pairs calibration with the layer regulariser).
  * ------------------------------------------------------------------------- */
@@ -339,7 +339,8 @@ int fdl_render_tabulated(const fdl_c64* layer_spec_dev, const float* d_dev, int 
  *   grad P^y_jk = sum_q T_jk(q) w_y(q), T_jk = dE_q / d<P_jk, w_q>.
  *   grad_shifts_dev [m][n][2] double; loss_dev [1] double; workspace of at
  *   least fdl_calib_relaxed_workspace(m, n, Q) bytes; the per-bin LDS of
- *   fdl_calib_grad plus 16 m n bytes must fit one block (FDL_ESHAPE).
+ *   fdl_calib_grad (without the max) plus 16 m n + 2048 bytes must fit one
+ *   block (FDL_ESHAPE).
  * fdl_gd_step_relaxed: P <- P - alpha grad_P / (eps_g + ||grad_P||^2), the
  *   update of Sec. V-B with the norm over all 2 m n entries, in FP64, stored
  *   back to the float shifts (m n <= 2^24).

@@ -49,13 +49,22 @@ __host__ __device__ inline CalibLayout calib_layout(int m, int n, int C, int mod
     o.y = at; at += 2 * n * C;
     o.v = at; at += 2 * m * C;
     o.gam = at; at += m;
-    o.Wm = at; at += 2 * n * n;
+    o.Wm = o.L;   // L is dead once the sweeps are done, before Wm is formed
   } else {
     o.P = o.w = o.y = o.v = o.gam = o.Wm = 0;
   }
-  o.gP = at;   // relaxed model: running gradient of the shifts, [m][n][2]
-  if (relaxed) at += 2 * m * n;
-  o.red = at; at += 256;
+  if (relaxed) {
+    o.gP = at;   // relaxed model: running gradient of the shifts, [m][n][2]
+    at += 2 * m * n;
+    o.red = at;
+    at += 256;
+  } else {
+    // the final block reduction runs after the bin loop, when every other
+    // region is dead
+    o.gP = 0;
+    o.red = 0;
+    if (at < 256) at = 256;
+  }
   o.total = at;
   return o;
 }
@@ -82,15 +91,15 @@ __device__ __forceinline__ double reg_entry(int reg, int i, int k, int n, double
   return (i == k) ? lambda : 0.0;
 }
 
-// At least 2 blocks per CU; the kernel compiles to about 160 VGPRs, which
-// leaves room for 3 (as many as the leave-one-out LDS of 49 views and 16
-// layers allows).  Asking for 3 forces a tighter allocation that measured
-// slower; inner loops are unrolled by 4 (8 measured slower too).
+// 4 blocks per CU (128 VGPRs): the leave-one-out layout of 49 views and 16
+// layers takes 40 KB of LDS, so four bins are in flight per CU.  The grid is
+// sized from the LDS, so the register budget must allow as many blocks; 2 and
+// 3 blocks per CU measured slower.  Inner loops are unrolled by 4.
 // RELAXED: the relaxed model of Sec. VIII-B, phases <P_jk, w> from a free
 // shift matrix and the gradient with respect to every shift (Eq. gradP with
 // both components) instead of the chain rule to u and d.
 template <bool RELAXED>
-__global__ __launch_bounds__(256, 2) void k_calib(CalibParams P) {
+__global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
   constexpr int NT = 256;
   extern __shared__ double sm[];
   const int m = P.m, n = P.n, C = P.C;
@@ -401,12 +410,13 @@ __global__ __launch_bounds__(256) void k_calib_reduce(CalibParams P, int nblocks
   }
 }
 
-// Blocks resident at once: 256 CUs x (blocks whose LDS fits one CU), at most
-// the workspace bound.
+// Blocks resident at once: 256 CUs x (blocks whose LDS fits one CU, at most
+// the 4 the register budget of k_calib allows), at most the workspace bound.
+// A grid larger than what is resident would leave a tail of late blocks.
 int calib_blocks(int Q, size_t lds_per_block) {
-  size_t per_cu = lds_per_block ? (size_t)163840 / lds_per_block : 8;
+  size_t per_cu = lds_per_block ? (size_t)163840 / lds_per_block : 4;
   if (per_cu < 1) per_cu = 1;
-  if (per_cu > 8) per_cu = 8;
+  if (per_cu > 4) per_cu = 4;
   size_t nb = 256 * per_cu;
   if (nb > (size_t)kCalibMaxBlocks) nb = kCalibMaxBlocks;
   return Q < (int)nb ? Q : (int)nb;
