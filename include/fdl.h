@@ -16,7 +16,14 @@
  *     and a leave-one-out variant with a hand-written adjoint,
  *   - the normalised gradient step on (u, d) (Sec. V-B),
  *   - a batched construction of many uneven light fields in one persistent
- *     launch (a plan object, so the launch can be captured in a HIP graph).
+ *     launch (a plan object, so the launch can be captured in a HIP graph),
+ *   - construction from input views taken with their own apertures
+ *     (Eq. AMatGeneral: focal stacks, wide-aperture and mixed inputs),
+ *   - the relaxed model of Sec. VIII-B (a free shift per view and layer):
+ *     its calibration gradient and update, construction and rendering,
+ *   - drawn apertures (Sec. VI): the spectrum of a zero-padded aperture image
+ *     and rendering with it,
+ *   - the view regulariser over a finite camera-plane region (Eq. GTG).
  *
  * Conventions shared by every entry point
  * ---------------------------------------
