@@ -358,8 +358,8 @@ def main():
                     help="also run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build measures one GPU only (the FDL path is run on one MI355X; "
-              "multi-GPU sharding is described, not built). Use --gpus 1.", file=sys.stderr)
+        print("bench.py: the FDL path runs on one MI355X; more than one GPU is not supported "
+              "(the sharding is designed, not implemented). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

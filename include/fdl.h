@@ -68,7 +68,7 @@ enum fdl_status {
   FDL_ENOMEM = -3,        /* workspace too small / device allocation failed */
   FDL_EHIP = -4,          /* HIP runtime or launch error */
   FDL_ENUMERIC = -5,      /* reserved for numerical failures reported on the host */
-  FDL_EUNSUPPORTED = -6   /* valid request this build does not implement */
+  FDL_EUNSUPPORTED = -6   /* valid request this library version does not implement */
 };
 
 enum fdl_reg {
@@ -89,7 +89,7 @@ enum fdl_aperture {
   FDL_AP_IMAGE = 3        /* drawn aperture scaled to half-side rho (fdl_render_tabulated); pinhole elsewhere */
 };
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define FDL_MAX_LAYERS 32
 #define FDL_MAX_CHANNELS 4
 

@@ -85,7 +85,7 @@ const char* fdl_status_string(int code) {
     case FDL_ENOMEM: return "out of memory or workspace too small";
     case FDL_EHIP: return "HIP runtime error";
     case FDL_ENUMERIC: return "numerical failure";
-    case FDL_EUNSUPPORTED: return "not supported by this build";
+    case FDL_EUNSUPPORTED: return "not supported by this library version";
     default: return "unknown status";
   }
 }
