@@ -63,7 +63,7 @@ def load_counters():
     """The committed rocprofv3 counter record of the construction kernel (HBM
     bytes and VALU instructions per launch), or {} when the kernel source
     changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "construct_config2_traffic.json")
+    path = os.path.join(ROOT, "profiles", "construct_9x9_512rgb_traffic.json")
     try:
         with open(path) as f:
             rec = json.load(f)
@@ -168,7 +168,7 @@ def systems(fdl, synth, dev, serve_seconds: float):
     g = torch.Generator(device=dev).manual_seed(3)
     items = []
     for i in range(64):
-        gsz, side, n = synth.config3_shape(i)
+        gsz, side, n = synth.uneven_light_field_shape(i)
         u = torch.from_numpy(synth.centered_grid_positions(gsz)).to(dev)
         m = u.shape[0]
         spec = torch.randn((m, 1, side, side // 2 + 1), dtype=torch.complex64, device=dev, generator=g)
@@ -212,26 +212,26 @@ def systems(fdl, synth, dev, serve_seconds: float):
 
     # calibration loop (7x7 / 256^2 / 16 layers, LOO loss, 4096 bins per step):
     # 200 steps issued eagerly vs the same steps captured once in a HIP graph
-    c5, u5_0, d5_0 = synth.config5()
-    l5 = fdl.rfft2(torch.from_numpy(c5.layers).to(dev))
-    p5 = torch.zeros((c5.m, 5), dtype=torch.float32)
-    p5[:, 0:2] = torch.from_numpy(c5.u)
-    v5 = fdl.irfft2(fdl.render(l5, torch.from_numpy(c5.d).to(dev), fdl.view_records(p5.to(dev)), c5.H, c5.W),
-                    c5.H, c5.W) + torch.from_numpy(c5.noise).to(dev)
+    lfc, u5_0, d5_0 = synth.lf_7x7_256_calib()
+    l5 = fdl.rfft2(torch.from_numpy(lfc.layers).to(dev))
+    p5 = torch.zeros((lfc.m, 5), dtype=torch.float32)
+    p5[:, 0:2] = torch.from_numpy(lfc.u)
+    v5 = fdl.irfft2(fdl.render(l5, torch.from_numpy(lfc.d).to(dev), fdl.view_records(p5.to(dev)), lfc.H, lfc.W),
+                    lfc.H, lfc.W) + torch.from_numpy(lfc.noise).to(dev)
     b5 = fdl.rfft2(v5)
-    F5 = c5.H * (c5.W // 2 + 1)
+    F5 = lfc.H * (lfc.W // 2 + 1)
     nsteps = 200
     rng = np.random.default_rng(5)
     subs = torch.from_numpy(np.stack([synth.frequency_subset(F5, 4096, rng) for _ in range(nsteps)])).to(dev)
     u5 = torch.from_numpy(u5_0).to(dev)
     d5 = torch.from_numpy(d5_0).to(dev)
-    g5 = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((c5.m, 2), dtype=torch.float64, device=dev),
-          torch.empty(c5.n, dtype=torch.float64, device=dev))
-    ws = torch.empty(fdl.calib_workspace_bytes(c5.m, c5.n, 4096), dtype=torch.uint8, device=dev)
+    g5 = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((lfc.m, 2), dtype=torch.float64, device=dev),
+          torch.empty(lfc.n, dtype=torch.float64, device=dev))
+    ws = torch.empty(fdl.calib_workspace_bytes(lfc.m, lfc.n, 4096), dtype=torch.uint8, device=dev)
 
     def loop():
         for i in range(nsteps):
-            fdl.calib_grad(b5, u5, d5, c5.H, c5.W, c5.lam, c5.eps, c5.reg, fdl.LOSS_LOO, subs[i], out=g5, ws=ws)
+            fdl.calib_grad(b5, u5, d5, lfc.H, lfc.W, lfc.lam, lfc.eps, lfc.reg, fdl.LOSS_LOO, subs[i], out=g5, ws=ws)
             fdl.gd_step(u5, d5, g5[1], g5[2], 0.2, 1e-6)
 
     t_eager = timed(loop, reps=2)
@@ -252,49 +252,49 @@ def systems(fdl, synth, dev, serve_seconds: float):
     # gradient steps (FIT objective, 4096 bins each) from the rank-1 shifts,
     # then the denoising pass (layers over all bins with the final shifts, the
     # 49 input views rendered back, inverse DFT)
-    P_true = (torch.from_numpy(c5.d)[None, :, None] * torch.from_numpy(c5.u)[:, None, :]
-              + torch.from_numpy(synth.shift_deviations(c5.m, c5.n, np.random.default_rng(57))))
+    P_true = (torch.from_numpy(lfc.d)[None, :, None] * torch.from_numpy(lfc.u)[:, None, :]
+              + torch.from_numpy(synth.shift_deviations(lfc.m, lfc.n, np.random.default_rng(57))))
     P_true = P_true.to(dev).contiguous()
-    vr = fdl.irfft2(fdl.render_relaxed(l5, P_true, c5.H, c5.W), c5.H, c5.W) + torch.from_numpy(c5.noise).to(dev)
+    vr = fdl.irfft2(fdl.render_relaxed(l5, P_true, lfc.H, lfc.W), lfc.H, lfc.W) + torch.from_numpy(lfc.noise).to(dev)
     br = fdl.rfft2(vr)
-    P0 = (torch.from_numpy(c5.d)[None, :, None] * torch.from_numpy(c5.u)[:, None, :]).to(dev).contiguous()
+    P0 = (torch.from_numpy(lfc.d)[None, :, None] * torch.from_numpy(lfc.u)[:, None, :]).to(dev).contiguous()
     Pw = P0.clone()
     rsteps = 200
     rsubs = torch.from_numpy(np.stack([synth.frequency_subset(F5, 4096, rng) for _ in range(rsteps)])).to(dev)
     gr_out = (torch.empty(1, dtype=torch.float64, device=dev),
-              torch.empty((c5.m, c5.n, 2), dtype=torch.float64, device=dev))
-    wsr = torch.empty(fdl.calib_relaxed_workspace_bytes(c5.m, c5.n, 4096), dtype=torch.uint8, device=dev)
+              torch.empty((lfc.m, lfc.n, 2), dtype=torch.float64, device=dev))
+    wsr = torch.empty(fdl.calib_relaxed_workspace_bytes(lfc.m, lfc.n, 4096), dtype=torch.uint8, device=dev)
 
     def relaxed_loop():
         Pw.copy_(P0)
         for i in range(rsteps):
-            fdl.calib_grad_relaxed(br, Pw, c5.H, c5.W, c5.lam, c5.eps, c5.reg, fdl.LOSS_FIT, rsubs[i], out=gr_out,
+            fdl.calib_grad_relaxed(br, Pw, lfc.H, lfc.W, lfc.lam, lfc.eps, lfc.reg, fdl.LOSS_FIT, rsubs[i], out=gr_out,
                                    ws=wsr)
             fdl.gd_step_relaxed(Pw, gr_out[1], 0.2, 1e-6)
 
-    lay_r = torch.empty((c5.n, 1, c5.H, c5.W // 2 + 1), dtype=torch.complex64, device=dev)
-    out_r = torch.empty((c5.m, 1, c5.H, c5.W // 2 + 1), dtype=torch.complex64, device=dev)
-    img_r = torch.empty((c5.m, 1, c5.H, c5.W), dtype=torch.float32, device=dev)
+    lay_r = torch.empty((lfc.n, 1, lfc.H, lfc.W // 2 + 1), dtype=torch.complex64, device=dev)
+    out_r = torch.empty((lfc.m, 1, lfc.H, lfc.W // 2 + 1), dtype=torch.complex64, device=dev)
+    img_r = torch.empty((lfc.m, 1, lfc.H, lfc.W), dtype=torch.float32, device=dev)
 
     def denoise():
-        fdl.construct_relaxed(br, Pw, c5.H, c5.W, c5.lam, c5.eps, c5.reg, out=lay_r)
-        fdl.render_relaxed(lay_r, Pw, c5.H, c5.W, out=out_r)
-        fdl.irfft2(out_r, c5.H, c5.W, out=img_r)
+        fdl.construct_relaxed(br, Pw, lfc.H, lfc.W, lfc.lam, lfc.eps, lfc.reg, out=lay_r)
+        fdl.render_relaxed(lay_r, Pw, lfc.H, lfc.W, out=out_r)
+        fdl.irfft2(out_r, lfc.H, lfc.W, out=img_r)
 
     t_rloop = timed(relaxed_loop, reps=2)
     t_den = timed(denoise, reps=5)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
     ev[0].record()
     for _ in range(5):
-        fdl.construct_relaxed(br, Pw, c5.H, c5.W, c5.lam, c5.eps, c5.reg, out=lay_r)
+        fdl.construct_relaxed(br, Pw, lfc.H, lfc.W, lfc.lam, lfc.eps, lfc.reg, out=lay_r)
     ev[1].record()
     for _ in range(5):
-        fdl.render_relaxed(lay_r, Pw, c5.H, c5.W, out=out_r)
+        fdl.render_relaxed(lay_r, Pw, lfc.H, lfc.W, out=out_r)
     ev[2].record()
     torch.cuda.synchronize()
     # denoising error against the noise-free relaxed-model views, with the
     # fitted shifts, the rank-1 start and the true shifts
-    clean = vr - torch.from_numpy(c5.noise).to(dev)
+    clean = vr - torch.from_numpy(lfc.noise).to(dev)
 
     def err(img):
         return float(torch.linalg.vector_norm(img - clean) / torch.linalg.vector_norm(clean))
@@ -324,14 +324,14 @@ def systems(fdl, synth, dev, serve_seconds: float):
 
     if serve_seconds > 0:
         from paper_1901_06919_amd.serve import FDLServer, PoolEntry
-        c2 = synth.config2(H=8, W=8)          # positions / disparities only
+        lfb = synth.lf_9x9_512_rgb(H=8, W=8)          # positions / disparities only
         pool = []
-        d = torch.from_numpy(c2.d)
+        d = torch.from_numpy(lfb.d)
         for i in range(8):
             spec = torch.randn((81, 3, 512, 257), dtype=torch.complex64, device=dev, generator=g)
-            pool.append(PoolEntry(spec, torch.from_numpy(c2.u).to(dev), d, d.to(dev), 512, 512, 1e-3, 1e-3, 0))
+            pool.append(PoolEntry(spec, torch.from_numpy(lfb.u).to(dev), d, d.to(dev), 512, 512, 1e-3, 1e-3, 0))
         for rate in (200.0, 1000.0):
-            reqs = synth.config4_requests(rate=rate, duration=serve_seconds, pool=8, seed=4)
+            reqs = synth.serving_requests(rate=rate, duration=serve_seconds, pool=8, seed=4)
             for i, r in enumerate(reqs):
                 r.rid = i
             res = {}
@@ -372,41 +372,41 @@ def main():
     torch.cuda.set_device(dev)
 
     # ---- set-up (untimed): synthetic workload resident in HBM ----
-    c2 = synth.config2()
-    H, W = c2.H, c2.W
-    m, n, C = c2.m, c2.n, c2.C
+    lfb = synth.lf_9x9_512_rgb()
+    H, W = lfb.H, lfb.W
+    m, n, C = lfb.m, lfb.n, lfb.C
     F = H * (W // 2 + 1)
-    layers = torch.from_numpy(c2.layers).to(dev)
-    u = torch.from_numpy(c2.u).to(dev)
-    d_dev = torch.from_numpy(c2.d).to(dev)
-    d_host = torch.from_numpy(c2.d).clone()
+    layers = torch.from_numpy(lfb.layers).to(dev)
+    u = torch.from_numpy(lfb.u).to(dev)
+    d_dev = torch.from_numpy(lfb.d).to(dev)
+    d_host = torch.from_numpy(lfb.d).clone()
     pin = torch.zeros((m, 5), dtype=torch.float32)
-    pin[:, 0:2] = torch.from_numpy(c2.u)
+    pin[:, 0:2] = torch.from_numpy(lfb.u)
     pin_rec = fdl.view_records(pin.to(dev))
-    views_rec = fdl.view_records(torch.from_numpy(c2.views).to(dev))
+    views_rec = fdl.view_records(torch.from_numpy(lfb.views).to(dev))
     lspec = fdl.rfft2(layers)
     vspec = fdl.render(lspec, d_dev, pin_rec, H, W)
-    views = fdl.irfft2(vspec, H, W) + torch.from_numpy(c2.noise).to(dev)
+    views = fdl.irfft2(vspec, H, W) + torch.from_numpy(lfb.noise).to(dev)
     del lspec, vspec, layers
 
-    c5, u5_0, d5_0 = synth.config5()
-    l5 = fdl.rfft2(torch.from_numpy(c5.layers).to(dev))
-    p5 = torch.zeros((c5.m, 5), dtype=torch.float32)
-    p5[:, 0:2] = torch.from_numpy(c5.u)
-    v5 = fdl.irfft2(fdl.render(l5, torch.from_numpy(c5.d).to(dev), fdl.view_records(p5.to(dev)), c5.H, c5.W),
-                    c5.H, c5.W) + torch.from_numpy(c5.noise).to(dev)
+    lfc, u5_0, d5_0 = synth.lf_7x7_256_calib()
+    l5 = fdl.rfft2(torch.from_numpy(lfc.layers).to(dev))
+    p5 = torch.zeros((lfc.m, 5), dtype=torch.float32)
+    p5[:, 0:2] = torch.from_numpy(lfc.u)
+    v5 = fdl.irfft2(fdl.render(l5, torch.from_numpy(lfc.d).to(dev), fdl.view_records(p5.to(dev)), lfc.H, lfc.W),
+                    lfc.H, lfc.W) + torch.from_numpy(lfc.noise).to(dev)
     b5 = fdl.rfft2(v5)
     del l5, v5
     u5 = torch.from_numpy(u5_0).to(dev)
     d5 = torch.from_numpy(d5_0).to(dev)
-    F5 = c5.H * (c5.W // 2 + 1)
+    F5 = lfc.H * (lfc.W // 2 + 1)
     Q5 = 4096
     rng = np.random.default_rng(5)
     nsub = args.warmup + args.steps
     subsets = torch.from_numpy(np.stack([synth.frequency_subset(F5, Q5, rng) for _ in range(nsub)])).to(dev)
-    g_out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((c5.m, 2), dtype=torch.float64, device=dev),
-             torch.empty(c5.n, dtype=torch.float64, device=dev))
-    ws5 = torch.empty(fdl.calib_workspace_bytes(c5.m, c5.n, Q5), dtype=torch.uint8, device=dev)
+    g_out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((lfc.m, 2), dtype=torch.float64, device=dev),
+             torch.empty(lfc.n, dtype=torch.float64, device=dev))
+    ws5 = torch.empty(fdl.calib_workspace_bytes(lfc.m, lfc.n, Q5), dtype=torch.uint8, device=dev)
 
     spec = torch.empty((m, C, H, W // 2 + 1), dtype=torch.complex64, device=dev)
     lay = torch.empty((n, C, H, W // 2 + 1), dtype=torch.complex64, device=dev)
@@ -429,13 +429,13 @@ def main():
         mark()
         fdl.rfft2(views, out=spec)
         mark()
-        fdl.construct(spec, u, d_host, H, W, c2.lam, c2.eps, c2.reg, out=lay)
+        fdl.construct(spec, u, d_host, H, W, lfb.lam, lfb.eps, lfb.reg, out=lay)
         mark()
         fdl.render(lay, d_dev, views_rec, H, W, out=rend)
         mark()
         fdl.irfft2(rend, H, W, out=img)
         mark()
-        fdl.calib_grad(b5, u5, d5, c5.H, c5.W, c5.lam, c5.eps, c5.reg, fdl.LOSS_LOO, subsets[i], out=g_out, ws=ws5)
+        fdl.calib_grad(b5, u5, d5, lfc.H, lfc.W, lfc.lam, lfc.eps, lfc.reg, fdl.LOSS_LOO, subsets[i], out=g_out, ws=ws5)
         mark()
         fdl.gd_step(u5, d5, g_out[1], g_out[2], 0.2, 1e-6)
         mark()
@@ -490,13 +490,13 @@ def main():
     hv[9:, 1] = hy.ravel()
     hrec = fdl.view_records(torch.from_numpy(hv).to(dev))
     hspec = spec[:18]
-    fdl.construct_views(hspec, hrec, d_host, H, W, c2.lam, c2.eps, c2.reg, out=lay)
+    fdl.construct_views(hspec, hrec, d_host, H, W, lfb.lam, lfb.eps, lfb.reg, out=lay)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(5):
-        fdl.construct_views(hspec, hrec, d_host, H, W, c2.lam, c2.eps, c2.reg, out=lay)
+        fdl.construct_views(hspec, hrec, d_host, H, W, lfb.lam, lfb.eps, lfb.reg, out=lay)
     e1.record()
     torch.cuda.synchronize()
     t_views = e0.elapsed_time(e1) / 5
@@ -512,7 +512,7 @@ def main():
     hexa = ((ay <= math.sqrt(3) / 2) & (math.sqrt(3) * ax + ay <= math.sqrt(3))).astype(np.float32)
     img_ap = torch.from_numpy(hexa).to(dev)
     tab = fdl.aperture_table(img_ap, pad_ap)
-    hv_img = torch.from_numpy(c2.views).clone()
+    hv_img = torch.from_numpy(lfb.views).clone()
     hv_img[:, 4] = fdl.AP_IMAGE
     rec_img = fdl.view_records(hv_img.to(dev))
     fdl.render_tabulated(lay, d_dev, rec_img, H, W, tab, S_ap, out=rend)
@@ -532,12 +532,12 @@ def main():
     # finite-region view regulariser (camera-plane square of side 8, the
     # extent of the 9x9 grid) on the benchmark construction
     fdl.rfft2(views, out=spec)
-    fdl.construct_region(spec, u, d_host, H, W, c2.lam, c2.eps, 8.0, out=lay)
+    fdl.construct_region(spec, u, d_host, H, W, lfb.lam, lfb.eps, 8.0, out=lay)
     torch.cuda.synchronize()
     er = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
     er[0].record()
     for _ in range(5):
-        fdl.construct_region(spec, u, d_host, H, W, c2.lam, c2.eps, 8.0, out=lay)
+        fdl.construct_region(spec, u, d_host, H, W, lfb.lam, lfb.eps, 8.0, out=lay)
     er[1].record()
     torch.cuda.synchronize()
     t_reg = er[0].elapsed_time(er[1]) / 5
@@ -558,7 +558,7 @@ def main():
 
     base = None
     if not args.no_cpu_baseline:
-        base = cpu_baseline(c2.u, c2.d)
+        base = cpu_baseline(lfb.u, lfb.d)
 
     out = {
         "metric": "layer-construction frequency solves/s",

@@ -146,7 +146,7 @@ def frequency_subset(F: int, Q: int, rng: np.random.Generator) -> np.ndarray:
 # The five workloads.
 # --------------------------------------------------------------------------
 
-def config1(seed: int = 0, H: int = 128, W: int = 128) -> LightFieldSpec:
+def lf_5x5_128(seed: int = 0, H: int = 128, W: int = 128) -> LightFieldSpec:
     """5x5 integer grid, 128^2, 1 channel, 8 layers linspace(-2,2,8),
     blurred-noise layers (sigma 2 px), view noise 0.01, lambda 1e-2,
     16 pinhole renders at uniform positions in [-2,2]^2."""
@@ -159,10 +159,10 @@ def config1(seed: int = 0, H: int = 128, W: int = 128) -> LightFieldSpec:
     views = render_requests(16, rng, 2.0, 0.0, 0.0, 0.0, shapes=(AP_PINHOLE,))
     views[:, 2:4] = 0.0
     d = np.linspace(-2.0, 2.0, n).astype(np.float32)
-    return LightFieldSpec(layers, u, d, noise, 1e-2, 1e-3, REG_VIEW2, views, seed, "config1")
+    return LightFieldSpec(layers, u, d, noise, 1e-2, 1e-3, REG_VIEW2, views, seed, "lf_5x5_128")
 
 
-def config2(seed: int = 2, H: int = 512, W: int = 512) -> LightFieldSpec:
+def lf_9x9_512_rgb(seed: int = 2, H: int = 512, W: int = 512) -> LightFieldSpec:
     """9x9 jittered grid (+-0.05), 512^2 RGB, 30 layers linspace(-3,3,30),
     1/f^2-spectrum layers, view noise 0.005, lambda 1e-3; 81 disk-aperture
     renders at the input positions, radius U[0,2], focus U[-3,3]."""
@@ -178,12 +178,12 @@ def config2(seed: int = 2, H: int = 512, W: int = 512) -> LightFieldSpec:
     views[:, 3] = rng.uniform(0.0, 2.0, size=m)
     views[:, 4] = AP_DISK
     d = np.linspace(-3.0, 3.0, n).astype(np.float32)
-    return LightFieldSpec(layers, u, d, noise, 1e-3, 1e-3, REG_VIEW2, views, seed, "config2")
+    return LightFieldSpec(layers, u, d, noise, 1e-3, 1e-3, REG_VIEW2, views, seed, "lf_9x9_512_rgb")
 
 
-def config3_instance(i: int, base_seed: int = 3000, sizes=(128, 256, 384, 512)) -> LightFieldSpec:
+def uneven_light_field(i: int, base_seed: int = 3000, sizes=(128, 256, 384, 512)) -> LightFieldSpec:
     """Instance i of the 64 uneven light fields: grid 3..9, side from ``sizes``,
-    8..32 layers linspace(-2,2,n), config-1 generator."""
+    8..32 layers linspace(-2,2,n), the generator of lf_5x5_128."""
     seed = base_seed + i
     rng = np.random.default_rng(seed)
     g = int(rng.integers(3, 10))
@@ -196,12 +196,12 @@ def config3_instance(i: int, base_seed: int = 3000, sizes=(128, 256, 384, 512)) 
     noise = (0.01 * rng.standard_normal((m, C, side, side))).astype(np.float32)
     views = np.zeros((0, 5), dtype=np.float32)
     d = np.linspace(-2.0, 2.0, n).astype(np.float32)
-    return LightFieldSpec(layers, u, d, noise, 1e-2, 1e-3, REG_VIEW2, views, seed, f"config3[{i}]")
+    return LightFieldSpec(layers, u, d, noise, 1e-2, 1e-3, REG_VIEW2, views, seed, f"uneven[{i}]")
 
 
-def config3_shape(i: int, base_seed: int = 3000, sizes=(128, 256, 384, 512)):
+def uneven_light_field_shape(i: int, base_seed: int = 3000, sizes=(128, 256, 384, 512)):
     """(grid side g, image side, layers n) of instance i -- the first three
-    draws of :func:`config3_instance`, without generating the images."""
+    draws of :func:`uneven_light_field`, without generating the images."""
     rng = np.random.default_rng(base_seed + i)
     g = int(rng.integers(3, 10))
     side = int(rng.choice(np.asarray(sizes)))
@@ -209,9 +209,9 @@ def config3_shape(i: int, base_seed: int = 3000, sizes=(128, 256, 384, 512)):
     return g, side, n
 
 
-def config5(seed: int = 5, H: int = 256, W: int = 256):
+def lf_7x7_256_calib(seed: int = 5, H: int = 256, W: int = 256):
     """7x7 integer grid, 256^2, 1 channel, 16 layers linspace(-2,2,16),
-    config-1 generator; returns (spec, u_init, d_init) with the start point
+    the generator of lf_5x5_128; returns (spec, u_init, d_init) with the start point
     perturbed by N(0,0.3^2) (positions) and N(0,0.2^2) (disparities)."""
     rng = np.random.default_rng(seed)
     n, C, R = 16, 1, 3
@@ -223,7 +223,7 @@ def config5(seed: int = 5, H: int = 256, W: int = 256):
     u0 = (u + 0.3 * rng.standard_normal(u.shape)).astype(np.float32)
     d0 = (d + 0.2 * rng.standard_normal(d.shape)).astype(np.float32)
     spec = LightFieldSpec(layers, u, d, noise, 1e-2, 1e-3, REG_LAYER2,
-                          np.zeros((0, 5), np.float32), seed, "config5")
+                          np.zeros((0, 5), np.float32), seed, "lf_7x7_256_calib")
     return spec, u0, d0
 
 
@@ -245,7 +245,7 @@ class Request:
     view: np.ndarray      # [5] float32 (render only)
 
 
-def config4_requests(rate: float = 200.0, duration: float = 60.0, pool: int = 8,
+def serving_requests(rate: float = 200.0, duration: float = 60.0, pool: int = 8,
                      construct_frac: float = 0.2, seed: int = 4) -> List[Request]:
     """Open-loop Poisson stream: 20% construct, 80% render against a random
     resident light field, position U[-4,4]^2, disk or square (p=1/2),

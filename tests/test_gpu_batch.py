@@ -22,7 +22,7 @@ def _items(count, sizes=(128, 256, 384, 512), seed=0):
     rng = np.random.default_rng(seed)
     items = []
     for i in range(count):
-        g, side, n = synth.config3_shape(i, sizes=sizes)
+        g, side, n = synth.uneven_light_field_shape(i, sizes=sizes)
         u = synth.centered_grid_positions(g)
         m = u.shape[0]
         H = W = side

@@ -57,16 +57,16 @@ def test_calib_small_all_bins(mode, m, n, C, H, W, reg):
     assert rel(gd2.cpu().numpy(), gd) < 1e-6
 
 
-def _config5_inputs():
-    spec, u0, d0 = synth.config5()
+def _calib_inputs():
+    spec, u0, d0 = synth.lf_7x7_256_calib()
     views = O.forward_views(spec.layers.astype(np.float64), spec.u, spec.d) + spec.noise
     b = O.rfft2(views.astype(np.float32)).astype(np.complex64)
     return spec, u0, d0, b
 
 
 @pytest.mark.parametrize("mode,Q", [(O.LOSS_FIT, 4096), (O.LOSS_LOO, 1024)])
-def test_calib_config5_sampled_bins(mode, Q):
-    spec, u0, d0, b = _config5_inputs()
+def test_calib_7x7_256_sampled_bins(mode, Q):
+    spec, u0, d0, b = _calib_inputs()
     H, W = spec.H, spec.W
     F = H * (W // 2 + 1)
     S = synth.frequency_subset(F, Q, np.random.default_rng(55))
@@ -74,7 +74,7 @@ def test_calib_config5_sampled_bins(mode, Q):
                                   spec.lam, spec.eps, spec.reg, mode, S)
     l2, gu2, gd2 = fdl().calib_grad(dev(b), dev(u0), dev(d0), H, W, spec.lam, spec.eps, spec.reg, mode, dev(S))
     torch.cuda.synchronize()
-    print(f"config5 mode={mode} Q={Q}: loss {L:.8e} vs {l2.item():.8e}; rel gu {rel(gu2.cpu(), gu):.2e} "
+    print(f"7x7/256 mode={mode} Q={Q}: loss {L:.8e} vs {l2.item():.8e}; rel gu {rel(gu2.cpu(), gu):.2e} "
           f"gd {rel(gd2.cpu(), gd):.2e}")
     assert abs(l2.item() - L) <= 1e-6 * abs(L)
     assert rel(gu2.cpu().numpy(), gu) < 1e-5
@@ -97,10 +97,10 @@ def _press_loss_all_bins(b, u, d, H, W, lam, eps):
     return float(np.sum(np.abs(r / (1.0 - h)[:, :, None]) ** 2))
 
 
-def test_loo_adjoint_vs_finite_differences_config5_all_bins():
+def test_loo_adjoint_vs_finite_differences_7x7_256_all_bins():
     """Hand-written LOO adjoint (all F = 33,024 bins) against FP64 central
     differences (h = 1e-6) of the LOO loss, on a spread of coordinates."""
-    spec, u0, d0, b = _config5_inputs()
+    spec, u0, d0, b = _calib_inputs()
     H, W = spec.H, spec.W
     l2, gu2, gd2 = fdl().calib_grad(dev(b), dev(u0), dev(d0), H, W, spec.lam, spec.eps, spec.reg, O.LOSS_LOO, None)
     torch.cuda.synchronize()
@@ -132,7 +132,7 @@ def test_loo_adjoint_vs_finite_differences_config5_all_bins():
 
 
 def test_calib_is_deterministic():
-    spec, u0, d0, b = _config5_inputs()
+    spec, u0, d0, b = _calib_inputs()
     H, W = spec.H, spec.W
     S = dev(synth.frequency_subset(H * (W // 2 + 1), 4096, np.random.default_rng(9)))
     a = [t.clone() for t in fdl().calib_grad(dev(b), dev(u0), dev(d0), H, W, spec.lam, spec.eps, spec.reg, 1, S)]
@@ -160,7 +160,7 @@ def test_calibration_trajectory_first_steps():
     """20 LOO gradient steps (alpha 0.2, fresh 512-bin subset per step, passed
     to both sides) on the 7x7 / 256^2 / 16-layer workload: parameters after
     every step within 1e-4 (relative L2) of the oracle's trajectory."""
-    spec, u0, d0, b = _config5_inputs()
+    spec, u0, d0, b = _calib_inputs()
     H, W = spec.H, spec.W
     F = H * (W // 2 + 1)
     rng = np.random.default_rng(505)

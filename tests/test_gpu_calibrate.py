@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 
 
 def _inputs():
-    spec, u0, d0 = synth.config5()
+    spec, u0, d0 = synth.lf_7x7_256_calib()
     views = O.forward_views(spec.layers.astype(np.float64), spec.u, spec.d) + spec.noise
     b = O.rfft2(views.astype(np.float32)).astype(np.complex64)
     return spec, torch.from_numpy(u0).cuda(), torch.from_numpy(d0).cuda(), torch.from_numpy(b).cuda()

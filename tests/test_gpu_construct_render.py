@@ -63,9 +63,9 @@ def test_construct_matches_oracle(m, n, C, H, W, uniform, reg):
     assert err < TOL
 
 
-def test_construct_config1_full_size():
-    """Config 1 at full size (5x5 views, 128^2, 8 layers), views from the oracle's forward model."""
-    spec_in = synth.config1()
+def test_construct_5x5_128_full_size():
+    """The 5x5-view light field at full size (128^2, 8 layers), views from the oracle's forward model."""
+    spec_in = synth.lf_5x5_128()
     views = O.forward_views(spec_in.layers.astype(np.float64), spec_in.u, spec_in.d) + spec_in.noise
     H, W = spec_in.H, spec_in.W
     b = O.rfft2(views.astype(np.float32)).astype(np.complex64)
@@ -74,7 +74,7 @@ def test_construct_config1_full_size():
     got = fdl().construct(dev(b), dev(spec_in.u), dev(spec_in.d), H, W, spec_in.lam, spec_in.eps, spec_in.reg)
     torch.cuda.synchronize()
     err = O.rel_l2(got.cpu().numpy(), ref)
-    print(f"config1 construct rel_l2 = {err:.3e}")
+    print(f"5x5/128 construct rel_l2 = {err:.3e}")
     assert err < TOL
 
 
@@ -145,15 +145,15 @@ def test_render_wide_apertures():
     assert err < TOL
 
 
-def test_render_config2_views_reduced_resolution():
-    """Config-2 render requests (81 disk views at the input positions, radius
+def test_render_9x9_views_reduced_resolution():
+    """The benchmark's render requests (81 disk views at the input positions, radius
     U[0,2], focus U[-3,3]) over 30 layers of 1/f images at 64^2."""
-    spec_in = synth.config2(H=64, W=64)
+    spec_in = synth.lf_9x9_512_rgb(H=64, W=64)
     x = O.rfft2(spec_in.layers).astype(np.complex64)
     H, W = spec_in.H, spec_in.W
     ref = O.render(x.astype(np.complex128), spec_in.d.astype(np.float64), spec_in.views.astype(np.float64), H, W)
     got = fdl().render(dev(x), dev(spec_in.d), dev(spec_in.views), H, W)
     torch.cuda.synchronize()
     err = O.rel_l2(got.cpu().numpy(), ref)
-    print(f"config2 render (64^2) rel_l2 = {err:.3e}")
+    print(f"9x9 render (64^2) rel_l2 = {err:.3e}")
     assert err < TOL

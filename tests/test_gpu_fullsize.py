@@ -30,8 +30,8 @@ def _spectra(rng, shape):
     return (re + 1j * im).astype(np.complex64)
 
 
-def test_construct_config2_full_size_sampled_bins():
-    c2 = synth.config2()          # positions, disparities, lambda, eps and render views of the workload
+def test_construct_9x9_512_rgb_full_size_sampled_bins():
+    lfb = synth.lf_9x9_512_rgb()          # positions, disparities, lambda, eps and render views of the workload
     H, W = 512, 512
     Wh = W // 2 + 1
     F = H * Wh
@@ -39,12 +39,12 @@ def test_construct_config2_full_size_sampled_bins():
     spec = _spectra(rng, (81, 3, H, Wh))
     print("construct 81 views 512x512 RGB 30 layers, all bins on the GPU", flush=True)
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
-    x = fdl().construct(dev(spec), dev(c2.u), torch.from_numpy(c2.d), H, W, c2.lam, c2.eps, c2.reg, status=st)
+    x = fdl().construct(dev(spec), dev(lfb.u), torch.from_numpy(lfb.d), H, W, lfb.lam, lfb.eps, lfb.reg, status=st)
     torch.cuda.synchronize()
     edge = [0, 1, Wh - 1, (H // 2) * Wh, (H // 2) * Wh + Wh - 1, (H - 1) * Wh, F - 1]
     idx = np.unique(np.concatenate([synth.frequency_subset(F, 2048, rng), edge]))
-    ref = O.construct(spec.astype(np.complex128), c2.u.astype(np.float64), c2.d.astype(np.float64), H, W,
-                      c2.lam, c2.eps, c2.reg, freq_index=idx)
+    ref = O.construct(spec.astype(np.complex128), lfb.u.astype(np.float64), lfb.d.astype(np.float64), H, W,
+                      lfb.lam, lfb.eps, lfb.reg, freq_index=idx)
     got = x.cpu().numpy().reshape(30, 3, F)[:, :, idx]
     err = O.rel_l2(got, ref)
     worst = max(O.rel_l2(got[:, :, i], ref[:, :, i]) for i in range(len(idx)))
@@ -53,18 +53,18 @@ def test_construct_config2_full_size_sampled_bins():
     assert st.item() == 0
 
 
-def test_render_config2_full_size_sampled_views():
-    c2 = synth.config2()
+def test_render_9x9_512_rgb_full_size_sampled_views():
+    lfb = synth.lf_9x9_512_rgb()
     H, W = 512, 512
     Wh = W // 2 + 1
     rng = np.random.default_rng(951)
     layers = _spectra(rng, (30, 3, H, Wh))
     print("render 81 disk views, 512x512 RGB, 30 layers", flush=True)
-    out = fdl().render(dev(layers), dev(c2.d), dev(c2.views), H, W)
+    out = fdl().render(dev(layers), dev(lfb.d), dev(lfb.views), H, W)
     torch.cuda.synchronize()
-    radius = c2.views[:, 3]
+    radius = lfb.views[:, 3]
     pick = np.unique([0, 40, 80, int(np.argmax(radius)), int(np.argmin(radius)), 37])
-    ref = O.render(layers.astype(np.complex128), c2.d.astype(np.float64), c2.views[pick].astype(np.float64), H, W)
+    ref = O.render(layers.astype(np.complex128), lfb.d.astype(np.float64), lfb.views[pick].astype(np.float64), H, W)
     got = out.cpu().numpy()[pick]
     for i, v in enumerate(pick):
         e = O.rel_l2(got[i], ref[i])

@@ -133,7 +133,7 @@ def test_calib_relaxed_small_all_bins(mode, m, n, C, H, W, reg):
 def test_calib_relaxed_of_rank1_shifts_gives_calib_grad(mode):
     """Chain rule through P_jk = d_k u_j on the GPU outputs: the relaxed
     gradient contracted with d (and u) equals fdl_calib_grad's."""
-    spec, u0, d0 = synth.config5(H=64, W=64)
+    spec, u0, d0 = synth.lf_7x7_256_calib(H=64, W=64)
     rng = np.random.default_rng(750)
     b = _spectra(rng, u0.shape[0], 1, 64, 64)
     S = dev(synth.frequency_subset(64 * 33, 1024, rng))
@@ -153,7 +153,7 @@ def test_calib_relaxed_of_rank1_shifts_gives_calib_grad(mode):
 def _relaxed_workload():
     """The 7x7 / 256^2 / 16-layer light field whose views follow a relaxed
     model: rank-1 shifts d_k u_j plus sparse deviations, noise sigma 0.01."""
-    spec, u0, d0 = synth.config5()
+    spec, u0, d0 = synth.lf_7x7_256_calib()
     H, W = spec.H, spec.W
     m, n = spec.u.shape[0], spec.d.shape[0]
     dP = synth.shift_deviations(m, n, np.random.default_rng(57))
@@ -165,7 +165,7 @@ def _relaxed_workload():
 
 
 @pytest.mark.parametrize("mode,Q", [(O.LOSS_FIT, 4096), (O.LOSS_LOO, 512)])
-def test_calib_relaxed_config5_sampled_bins(mode, Q):
+def test_calib_relaxed_7x7_256_sampled_bins(mode, Q):
     spec, b, P0 = _relaxed_workload()
     H, W = spec.H, spec.W
     S = synth.frequency_subset(H * (W // 2 + 1), Q, np.random.default_rng(58))
@@ -173,7 +173,7 @@ def test_calib_relaxed_config5_sampled_bins(mode, Q):
                                      spec.reg, mode, S)
     l2, g2 = fdl().calib_grad_relaxed(dev(b), dev(P0), H, W, spec.lam, spec.eps, spec.reg, mode, dev(S))
     torch.cuda.synchronize()
-    print(f"relaxed config5 mode={mode} Q={Q}: loss {L:.8e} vs {l2.item():.8e}; rel grad {rel(g2.cpu(), g):.2e}")
+    print(f"relaxed 7x7/256 mode={mode} Q={Q}: loss {L:.8e} vs {l2.item():.8e}; rel grad {rel(g2.cpu(), g):.2e}")
     assert abs(l2.item() - L) <= 1e-6 * abs(L)
     assert rel(g2.cpu().numpy(), g) < 1e-5
 

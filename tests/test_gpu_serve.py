@@ -30,7 +30,7 @@ def test_serving_results_equal_alone_and_admission_respects_budget():
     import paper_1901_06919_amd as fdl
     from paper_1901_06919_amd.serve import FDLServer
     pool = _pool(3)
-    reqs = synth.config4_requests(rate=400.0, duration=1.0, pool=3, seed=4)
+    reqs = synth.serving_requests(rate=400.0, duration=1.0, pool=3, seed=4)
     for i, r in enumerate(reqs):
         r.rid = i
     # budget deliberately tight: a few renders or one construct at a time
