@@ -238,3 +238,23 @@ def test_relaxed_entry_points_reject_bad_arguments():
         m.calib_grad_relaxed(spec, P, 8, 8, 1e-2, 1e-3, O.REG_LAYER2, 7)
     with pytest.raises(ValueError):
         m.render_relaxed(dev(_spectra(rng, 3, 1, 8, 8)), dev(_shifts(rng, 2, 4)), 8, 8)
+
+
+def test_calib_relaxed_benchmark_shape_and_lds_limit():
+    """81 views, 30 layers, 3 channels: the paper loss fits one block's LDS
+    (124 KB) and matches the oracle on every bin of a small image; the
+    leave-one-out layout of the same shape (172 KB) is rejected."""
+    rng = np.random.default_rng(780)
+    H, W, m, n, C = 6, 8, 81, 30, 3
+    P = _shifts(rng, m, n, 1.0)
+    spec = _spectra(rng, m, C, H, W)
+    S = np.arange(H * (W // 2 + 1), dtype=np.int32)
+    L, g = O.calib_relaxed_loss_grad(spec.astype(np.complex128), P.astype(np.float64), H, W, 1e-2, 1e-3,
+                                     O.REG_LAYER2, O.LOSS_FIT, S)
+    l2, g2 = fdl().calib_grad_relaxed(dev(spec), dev(P), H, W, 1e-2, 1e-3, O.REG_LAYER2, O.LOSS_FIT, None)
+    torch.cuda.synchronize()
+    print(f"  loss {L:.6e} vs {l2.item():.6e}; rel grad {rel(g2.cpu(), g):.2e}")
+    assert abs(l2.item() - L) <= 1e-6 * abs(L)
+    assert rel(g2.cpu().numpy(), g) < 1e-6
+    with pytest.raises(fdl().FDLError):
+        fdl().calib_grad_relaxed(dev(spec), dev(P), H, W, 1e-2, 1e-3, O.REG_LAYER2, O.LOSS_LOO, None)
