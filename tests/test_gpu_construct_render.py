@@ -157,3 +157,34 @@ def test_render_9x9_views_reduced_resolution():
     err = O.rel_l2(got.cpu().numpy(), ref)
     print(f"9x9 render (64^2) rel_l2 = {err:.3e}")
     assert err < TOL
+
+
+def test_construct_and_render_at_the_size_limits():
+    """The largest sizes the entry points accept: 4096 views, 32 layers and
+    4 channels for construction (uniform and general disparities), 2000
+    views of 4 channels over 32 layers for rendering, on a small image."""
+    H, W = 8, 10
+    rng = np.random.default_rng(990)
+    m, n, C = 4096, 32, 4
+    u = rng.uniform(-4, 4, (m, 2)).astype(np.float32)
+    spec = O.rfft2(rng.standard_normal((m, C, H, W))).astype(np.complex64)
+    for d in (np.linspace(-2, 2, n).astype(np.float32), np.sort(rng.uniform(-2, 2, n)).astype(np.float32)):
+        print(f"construct m={m} n={n} C={C} uniform={bool(np.allclose(np.diff(d), np.diff(d)[0]))}", flush=True)
+        ref = O.construct(spec.astype(np.complex128), u.astype(np.float64), d.astype(np.float64), H, W, 1e-2, 1e-3,
+                          O.REG_VIEW2, chunk=16)
+        got = fdl().construct(dev(spec), dev(u), torch.from_numpy(d), H, W, 1e-2, 1e-3, O.REG_VIEW2)
+        torch.cuda.synchronize()
+        err = O.rel_l2(got.cpu().numpy(), ref)
+        print(f"  rel_l2 = {err:.3e}")
+        assert err < TOL
+    V = 2000
+    layers = O.rfft2(rng.standard_normal((n, C, H, W))).astype(np.complex64)
+    d = np.linspace(-2, 2, n).astype(np.float32)
+    views = _views(991, V, (O.AP_DISK, O.AP_SQUARE, O.AP_PINHOLE))
+    print(f"render V={V} n={n} C={C}", flush=True)
+    ref = O.render(layers.astype(np.complex128), d.astype(np.float64), views.astype(np.float64), H, W)
+    got = fdl().render(dev(layers), dev(d), dev(views), H, W)
+    torch.cuda.synchronize()
+    err = O.rel_l2(got.cpu().numpy(), ref)
+    print(f"  rel_l2 = {err:.3e}")
+    assert err < TOL
