@@ -585,6 +585,7 @@ def main():
         "construct_region": region_row,
         "roofline": roof,
         "cpu_baseline": base,
+        "gpu_over_cpu_oracle": (F / (ms_per_step * 1e-3)) / base["value"] if base else None,
     }
     if sysres is not None:
         out["batching"] = sysres.get("batching")
