@@ -205,11 +205,15 @@ int fdl_construct_views(const fdl_c64* view_spec_dev, const fdl_view* views_dev,
  *   it; the gradient back-propagates through M^-1 (hand-written adjoint).
  *
  *   loss_dev   [1] double, grad_u_dev [m][2] double, grad_d_dev [n] double.
+ *   status_dev int32 device counter or NULL: incremented once for every entry
+ *   of freq_idx_dev outside [0, F).  Such an index is clamped into [0, F) (the
+ *   nearest end) and that bin is used in its place, so no access leaves
+ *   view_spec_dev and the outputs stay finite; the result is then that of the
+ *   clamped index set.
  *   ws_dev / ws_bytes: device workspace of at least fdl_calib_workspace(m, n, Q)
  *   bytes (per-block partial sums; reduced deterministically on the device).
  * Requires 1 <= m <= 256, 1 <= n <= FDL_MAX_LAYERS, 1 <= C <= FDL_MAX_CHANNELS,
- * Q >= 1 when freq_idx_dev != NULL, every index in [0, F) (not checked: an
- * index outside [0, F) reads outside view_spec_dev), and the per-bin system
+ * Q >= 1 when freq_idx_dev != NULL, and the per-bin system
  * must fit the LDS one block may use on the device (160 KiB on MI355X):
  * 8 * max(2mn + 2n^2 + n + 4mC + 2nC + m + mn, 256) bytes for FIT, plus
  * 8 * (2nm + 4mC + 2nC + m) for LOO (FDL_ESHAPE otherwise; m = 49, n = 16,
@@ -222,7 +226,7 @@ int fdl_calib_grad(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const floa
                    int m, int n, int C, int H, int W, float lambda, float eps, int reg, int mode,
                    const int32_t* freq_idx_dev, int Q,
                    double* loss_dev, double* grad_u_dev, double* grad_d_dev,
-                   void* ws_dev, size_t ws_bytes, void* stream);
+                   int32_t* status_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
 /* The normalised gradient step of Sec. V-B on the device:
  *   u <- u - alpha grad_u / (eps_g + ||grad_u||^2),  d <- d - alpha grad_d / (eps_g + ||grad_d||^2)
@@ -233,7 +237,9 @@ int fdl_gd_step(fdl_f2* u_dev, float* d_dev, const double* grad_u_dev, const dou
 
 /* ---------------------------------------------------------------------------
  * Batched construction of uneven light fields (same mathematics as
- * fdl_construct for each light field) in ONE persistent kernel launch.
+ * fdl_construct for each light field) in one launch per channel/disparity
+ * class, or one launch per row-slot class, as the plan's mode selects (the
+ * autotuner picks the mode that measures fastest on the plan's own data).
  *
  * fdl_batch_plan_create reads a HOST array of B descriptors, validates them,
  * chooses the launch shape (defaults, or the autotuner's choice), and
@@ -260,7 +266,9 @@ typedef struct fdl_batch_plan fdl_batch_plan;
  * tile, one launch per group; mode 1 = persistent: a grid of (blocks per CU x
  * CUs) blocks pulls tiles from an atomic queue, one launch per group; mode 2
  * = flat single: every light field through the n <= 32 solver, so one launch
- * covers all light fields of a channel/disparity class.
+ * covers all light fields of a channel/disparity class; mode 3 = persistent
+ * single: the atomic queue of mode 1 over all light fields of a
+ * channel/disparity class through the n <= 32 solver (one launch per class).
  * Tiles are ordered largest light field first.  The disparities of each light
  * field are read once (blocking) and classified as fdl_construct does.
  * Argument errors as fdl_construct. */
@@ -274,8 +282,9 @@ int fdl_batch_plan_execute(const fdl_batch_plan* plan, void* stream);
  * launches, launches per execution. */
 int fdl_batch_plan_info(const fdl_batch_plan* plan, int64_t* total_bins, int32_t* grid, int32_t* launches);
 int fdl_batch_plan_launches(const fdl_batch_plan* plan);
-/* Autotuner: times the candidates {flat}, {flat single} and {persistent, chunk 1 or 4 tiles
- * per queue access, 1/2/4 blocks per CU} on the plan's own data (`reps` timed
+/* Autotuner: times the candidates {flat}, {flat single}, {persistent, chunk 1 or 4 tiles
+ * per queue access, 1/2/4 blocks per CU} and {persistent single, chunk 1 or 4, 1/2
+ * blocks per CU} on the plan's own data (`reps` timed
  * executions each after a warm-up, synchronising `stream`), keeps the fastest
  * and returns its time in best_ms.  Overwrites the plan's outputs; not
  * capturable. */
@@ -341,7 +350,8 @@ int fdl_render_tabulated(const fdl_c64* layer_spec_dev, const float* d_dev, int 
  *   denoised result): out_j(w) = sum_k exp(2 pi i <P_jk, w>) L_k(w) for the V
  *   rows of shifts_dev ([V][n]); out_spec_dev [V][C][H][W/2+1], FP32 phases.
  * fdl_calib_grad_relaxed: the calibration loss of fdl_calib_grad (FIT or
- *   LOO, same bins, scaling and limits) as a function of P, and its gradient
+ *   LOO, same bins, index clamping and status count, scaling and limits) as a
+ *   function of P, and its gradient
  *   (Eq. gradP with both components): grad P^x_jk = sum_q T_jk(q) w_x(q),
  *   grad P^y_jk = sum_q T_jk(q) w_y(q), T_jk = dE_q / d<P_jk, w_q>.
  *   grad_shifts_dev [m][n][2] double; loss_dev [1] double; workspace of at
@@ -360,7 +370,8 @@ int fdl_render_relaxed(const fdl_c64* layer_spec_dev, const fdl_f2* shifts_dev, 
 size_t fdl_calib_relaxed_workspace(int m, int n, int Q);
 int fdl_calib_grad_relaxed(const fdl_c64* view_spec_dev, const fdl_f2* shifts_dev, int m, int n, int C, int H, int W,
                            float lambda, float eps, int reg, int mode, const int32_t* freq_idx_dev, int Q,
-                           double* loss_dev, double* grad_shifts_dev, void* ws_dev, size_t ws_bytes, void* stream);
+                           double* loss_dev, double* grad_shifts_dev, int32_t* status_dev, void* ws_dev,
+                           size_t ws_bytes, void* stream);
 int fdl_gd_step_relaxed(fdl_f2* shifts_dev, const double* grad_shifts_dev, int m, int n, double alpha, double eps_g,
                         void* stream);
 

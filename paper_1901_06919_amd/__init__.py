@@ -69,7 +69,7 @@ def lib():
         L.fdl_calib_workspace.argtypes = [i32, i32, i32]
         L.fdl_calib_grad.restype = i32
         L.fdl_calib_grad.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, i32,
-                                     vp, i32, vp, vp, vp, vp, sz, vp]
+                                     vp, i32, vp, vp, vp, vp, vp, sz, vp]
         L.fdl_gd_step.restype = i32
         L.fdl_gd_step.argtypes = [vp, vp, vp, vp, i32, i32, f64, f64, vp]
     if hasattr(L, "fdl_batch_plan_create"):
@@ -106,7 +106,7 @@ def lib():
     L.fdl_calib_relaxed_workspace.argtypes = [i32, i32, i32]
     L.fdl_calib_grad_relaxed.restype = i32
     L.fdl_calib_grad_relaxed.argtypes = [vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, i32, vp, i32,
-                                         vp, vp, vp, sz, vp]
+                                         vp, vp, vp, vp, sz, vp]
     L.fdl_gd_step_relaxed.restype = i32
     L.fdl_gd_step_relaxed.argtypes = [vp, vp, i32, i32, f64, f64, vp]
     _lib = L
@@ -243,6 +243,13 @@ def render(layer_spec: torch.Tensor, d: torch.Tensor, views: torch.Tensor, H: in
     return out
 
 
+def _status_ptr(status: Optional[torch.Tensor]) -> int:
+    if status is None:
+        return 0
+    _check(status, torch.int32, (1,), "status")
+    return status.data_ptr()
+
+
 def calib_workspace_bytes(m: int, n: int, Q: int) -> int:
     return int(lib().fdl_calib_workspace(m, n, Q))
 
@@ -250,8 +257,10 @@ def calib_workspace_bytes(m: int, n: int, Q: int) -> int:
 def calib_grad(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int, W: int,
                lam: float, eps: float, reg: int, mode: int, freq_idx: Optional[torch.Tensor] = None,
                out: Optional[Tuple[torch.Tensor, torch.Tensor, torch.Tensor]] = None,
-               ws: Optional[torch.Tensor] = None):
-    """(loss [1] f64, grad_u [m,2] f64, grad_d [n] f64) (fdl_calib_grad)."""
+               ws: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None):
+    """(loss [1] f64, grad_u [m,2] f64, grad_d [n] f64) (fdl_calib_grad).
+    ``status`` (int32 [1] on the device, optional) counts indices of
+    ``freq_idx`` outside [0, F); the kernel clamps them."""
     m, C = view_spec.shape[:2]
     n = d.shape[0]
     _check(view_spec, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
@@ -274,7 +283,7 @@ def calib_grad(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     _call("fdl_calib_grad", view_spec.data_ptr(), u.data_ptr(), d.data_ptr(), m, n, C, H, W, float(lam),
           float(eps), int(reg), int(mode), fp, Q, loss.data_ptr(), gu.data_ptr(), gd.data_ptr(),
-          ws.data_ptr(), ws.numel(), _stream(view_spec))
+          _status_ptr(status), ws.data_ptr(), ws.numel(), _stream(view_spec))
     return loss, gu, gd
 
 
@@ -400,8 +409,10 @@ def calib_relaxed_workspace_bytes(m: int, n: int, Q: int) -> int:
 
 def calib_grad_relaxed(view_spec: torch.Tensor, shifts: torch.Tensor, H: int, W: int, lam: float, eps: float,
                        reg: int, mode: int, freq_idx: Optional[torch.Tensor] = None,
-                       out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, ws: Optional[torch.Tensor] = None):
-    """(loss [1] f64, grad_shifts [m, n, 2] f64) (fdl_calib_grad_relaxed)."""
+                       out: Optional[Tuple[torch.Tensor, torch.Tensor]] = None, ws: Optional[torch.Tensor] = None,
+                       status: Optional[torch.Tensor] = None):
+    """(loss [1] f64, grad_shifts [m, n, 2] f64) (fdl_calib_grad_relaxed); ``status`` as
+    :func:`calib_grad`."""
     m, C = view_spec.shape[:2]
     n = shifts.shape[1]
     _check(view_spec, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
@@ -423,7 +434,8 @@ def calib_grad_relaxed(view_spec: torch.Tensor, shifts: torch.Tensor, H: int, W:
     if ws is None or ws.numel() < need:
         ws = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     _call("fdl_calib_grad_relaxed", view_spec.data_ptr(), shifts.data_ptr(), m, n, C, H, W, float(lam), float(eps),
-          int(reg), int(mode), fp, Q, loss.data_ptr(), g.data_ptr(), ws.data_ptr(), ws.numel(), _stream(view_spec))
+          int(reg), int(mode), fp, Q, loss.data_ptr(), g.data_ptr(), _status_ptr(status), ws.data_ptr(), ws.numel(),
+          _stream(view_spec))
     return loss, g
 
 

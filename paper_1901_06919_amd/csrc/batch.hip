@@ -6,9 +6,11 @@
 // 16 teams of a block solve the tile's 16 bins with the same team solver as
 // the plain kernels.  Launch modes: flat (one block per tile, one launch per
 // channel/disparity/row-slot class), flat single (every light field through
-// the n <= 32 solver: one launch per channel/disparity class) and persistent
+// the n <= 32 solver: one launch per channel/disparity class), persistent
 // (a machine-sized grid pulling tiles from an atomic queue, one launch per
-// class; the last block resets the queue so replays need no memset).  The
+// class; the last block resets the queue so replays need no memset) and
+// persistent single (the queue over every light field of a channel/disparity
+// class through the n <= 32 solver: one launch when all share the class).  The
 // autotuner times the candidates on the plan's own data and keeps the
 // fastest.
 #include <algorithm>
@@ -62,7 +64,7 @@ __global__ __launch_bounds__(256, TOEP && R > 1 ? 2 : 1) void k_batched_flat(con
 // from an atomic queue; one launch per row-slot class R.  The last block out
 // resets the queue, so replays need no memset.
 template <int CT, bool TOEP, int R>
-__global__ __launch_bounds__(256) void k_batched_persistent(const ConstructParams* __restrict__ lfs,
+__global__ __launch_bounds__(256, TOEP && R > 1 ? 2 : 1) void k_batched_persistent(const ConstructParams* __restrict__ lfs,
                                                             const Tile* __restrict__ tiles, int ntiles, int chunk,
                                                             int* counters) {
   __shared__ TeamLds<R> s_team[16];
@@ -107,7 +109,7 @@ struct BatchLaunch {            // one launch over a group of tiles
 
 struct fdl_batch_plan {
   int B = 0;
-  int mode = 0;                 // 0 flat per row-slot class, 1 persistent, 2 flat single launch
+  int mode = 0;                 // 0 flat per row-slot class, 1 persistent, 2 flat single, 3 persistent single
   int chunk = 1;                // tiles claimed per queue access (persistent)
   int grid_per_cu = 2;          // resident blocks per CU (persistent)
   int64_t total_bins = 0;
@@ -123,15 +125,17 @@ namespace {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? FDL_OK : (e == hipErrorOutOfMemory ? FDL_ENOMEM : FDL_EHIP); }
 
+// compute units of the current device (queried on every plan build: no
+// process-wide cache, so plans on different devices size their own grids)
 int cu_count() {
-  static int cus = 0;
-  if (!cus) {
-    int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-      cus = 256;
-  }
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus <= 0)
+    cus = 256;
   return cus;
 }
+
+bool persistent_mode(int mode) { return mode == 1 || mode == 3; }
 
 double lf_cost(const fdl::ConstructParams& P) {
   // per-bin work of the team solver grows with m (views), C and the row slots
@@ -146,7 +150,7 @@ int build_tiles(fdl_batch_plan* p) {
   for (int i = 0; i < p->B; ++i) {
     const auto& P = p->host_params[i];
     const int ct = P.C == 1 ? 1 : (P.C <= 3 ? 3 : 4);
-    const int r = p->mode == 2 ? 2 : (P.n <= 16 ? 1 : 2);
+    const int r = (p->mode == 2 || p->mode == 3) ? 2 : (P.n <= 16 ? 1 : 2);
     bool found = false;
     for (auto& g : groups)
       if (g.ct == ct && g.toep == P.toeplitz && g.r == r) { g.lfs.push_back(i); found = true; break; }
@@ -163,7 +167,7 @@ int build_tiles(fdl_batch_plan* p) {
     for (int lf : g.lfs)
       for (int f0 = 0; f0 < p->host_params[lf].F; f0 += 16) tiles.push_back(fdl::Tile{lf, f0});
     L.ntiles = (int)tiles.size() - L.tile_off;
-    L.grid = p->mode == 1 ? std::max(1, std::min((L.ntiles + p->chunk - 1) / p->chunk, cu_count() * p->grid_per_cu))
+    L.grid = persistent_mode(p->mode) ? std::max(1, std::min((L.ntiles + p->chunk - 1) / p->chunk, cu_count() * p->grid_per_cu))
                           : L.ntiles;
     L.counters = p->d_counters + 2 * gi;
     p->launches.push_back(L);
@@ -184,7 +188,7 @@ int build_tiles(fdl_batch_plan* p) {
 template <int CT, bool TOEP>
 hipError_t go(const fdl_batch_plan* p, const BatchLaunch& L, hipStream_t s) {
   const fdl::Tile* t = p->d_tiles + L.tile_off;
-  if (p->mode != 1) {
+  if (!persistent_mode(p->mode)) {
     if (L.r == 1)
       hipLaunchKernelGGL((fdl::k_batched_flat<CT, TOEP, 1>), dim3(L.grid), dim3(256), 0, s, p->d_params, t);
     else
@@ -214,7 +218,7 @@ void classify(const float* d, int n, fdl::ConstructParams& P);
 extern "C" {
 
 int fdl_batch_plan_create(const fdl_lf_desc* descs_host, int B, int mode, fdl_batch_plan** plan_out) {
-  if (!descs_host || !plan_out || B < 1 || mode < 0 || mode > 2) return FDL_EINVAL;
+  if (!descs_host || !plan_out || B < 1 || mode < 0 || mode > 3) return FDL_EINVAL;
   *plan_out = nullptr;
   auto* p = new fdl_batch_plan();
   p->B = B;
@@ -290,14 +294,16 @@ int fdl_batch_plan_destroy(fdl_batch_plan* plan) {
 }
 
 // Autotuner: times every candidate setting -- flat per class, flat single
-// launch, persistent queue with chunk in {1, 4} x {1, 2, 4} blocks per CU -- with
+// launch, persistent queue (per class or single) with chunk in {1, 4} x
+// {1, 2, 4} blocks per CU -- with
 // `reps` executions each (after one warm-up) on `stream`, keeps the fastest
 // and reports its time.  Synchronises the stream; not for use under capture.
 int fdl_batch_plan_autotune(fdl_batch_plan* plan, int reps, void* stream, float* best_ms) {
   if (!plan || reps < 1) return FDL_EINVAL;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   struct Cand { int mode, chunk, grid; };
-  const Cand cands[] = {{0, 1, 1}, {2, 1, 1}, {1, 1, 1}, {1, 1, 2}, {1, 1, 4}, {1, 4, 1}, {1, 4, 2}, {1, 4, 4}};
+  const Cand cands[] = {{0, 1, 1}, {2, 1, 1}, {1, 1, 1}, {1, 1, 2}, {1, 1, 4}, {1, 4, 1}, {1, 4, 2}, {1, 4, 4},
+                        {3, 1, 1}, {3, 1, 2}, {3, 4, 1}, {3, 4, 2}};
   hipEvent_t a, b;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return FDL_EHIP;
   float best = 1e30f;
@@ -338,7 +344,7 @@ int fdl_batch_plan_get_tuning(const fdl_batch_plan* plan, int32_t* mode, int32_t
 }
 
 int fdl_batch_plan_set_tuning(fdl_batch_plan* plan, int32_t mode, int32_t chunk, int32_t grid_per_cu) {
-  if (!plan || mode < 0 || mode > 2 || chunk < 1 || chunk > 64 || grid_per_cu < 1 || grid_per_cu > 16)
+  if (!plan || mode < 0 || mode > 3 || chunk < 1 || chunk > 64 || grid_per_cu < 1 || grid_per_cu > 16)
     return FDL_EINVAL;
   plan->mode = mode;
   plan->chunk = chunk;

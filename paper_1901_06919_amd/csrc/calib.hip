@@ -125,10 +125,17 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
   double* gP = sm + o.gP;
   if constexpr (RELAXED)
     for (int i = t; i < 2 * m * n; i += NT) gP[i] = 0.0;
+  // Bin of sample q.  A caller's index outside [0, F) is clamped into it, so
+  // that no access leaves the spectra, and counted in P.status by the block
+  // that processes it.
+  auto bin_of = [&](int q) -> int {
+    const int raw = P.freq_idx ? P.freq_idx[q] : q;
+    return min(max(raw, 0), P.F - 1);
+  };
   float2 bnext[4];
   auto fetch = [&](int q) {
     if (q >= P.Q) return;
-    const int fq = P.freq_idx ? P.freq_idx[q] : q;
+    const int fq = bin_of(q);
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int i = t + s * NT;
@@ -138,7 +145,8 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
   fetch(blockIdx.x);
 
   for (int q = blockIdx.x; q < P.Q; q += gridDim.x) {
-    const int f = P.freq_idx ? P.freq_idx[q] : q;
+    const int f = bin_of(q);
+    if (t == 0 && P.status && P.freq_idx && (unsigned)P.freq_idx[q] >= (unsigned)P.F) atomicAdd(P.status, 1);
     double wx, wy;
     bin_freq(f, P.Wh, P.H, P.W, wx, wy);
     const double w2 = wx * wx + wy * wy, w4 = w2 * w2;

@@ -13,16 +13,23 @@
 //   2. The Gram matrix M = A^H A:
 //      TOEP (d an arithmetic progression up to rounding): only the first
 //        column's relatives are summed, R_q,t = sum_j p_j^q conj(A_j0) A_jt,
-//        q = 0..3, and M_{k,i} = sum_j exp(2 pi i (d_i - d_k) p_j) is
+//        q = 0..2, and M_{k,i} = sum_j exp(2 pi i (d_i - d_k) p_j) is
 //        recovered exactly from t = i - k and the rounding residue
 //        th = 2 pi [(d_i - d_k) - (d_t - d_0)]:
-//        M_{k,i} = R0 + i th R1 - th^2/2 R2 - i th^3/6 R3 (remainder
-//        (th p)^4/24 < 1e-15 when th |p| <= 3e-4, checked per bin);
+//        M_{k,i} = R0 + i th R1 - th^2/2 R2 (relative remainder below
+//        (th p)^3/6 < 5e-12 when th |p| <= 3e-4, checked per bin);
 //      general: row i accumulates conj(A_ji) A_jk with A_jk broadcast from
 //        the lane that owns layer k.
-//   3. M += lambda Gamma^H Gamma + eps I.
+//   3. The diagonal of lambda Gamma^H Gamma + eps I is added to each pivot as
+//      the factorisation reaches it (the diagonal registers hold only the
+//      Gram part); the off-diagonal bands of the layer regulariser are added
+//      to the lower triangle before.
 //   4. Right-looking Cholesky M = L L^H with rows in registers; column j is
 //      broadcast with DPP row_newbcast; non-positive pivots are counted.
+//      Rows n..16R-1 pad the system: their pivots are forced to 1, their
+//      unknowns to 0 (1/L_jj := 0) and their rows of L are cleared after the
+//      factorisation, so they never reach the live unknowns (the live block
+//      of L does not depend on later rows).
 //   5. Forward substitution (broadcast of y_j); backward substitution either
 //      with a 16-lane DPP reduction per unknown (R = 1) or, for R = 2, after
 //      transposing L through LDS so that lane k holds column k of L, with a
@@ -145,13 +152,12 @@ __device__ __forceinline__ cd expi_tab(const double2* __restrict__ tab, double d
   return cd{fma(e.x, cx, -e.y * sx), fma(e.y, cx, e.x * sx)};
 }
 
-// R0 in FP64; R1..R3 only enter through the residue corrections (|th| below
-// about 1e-5), where FP32 keeps the entries exact to FP64 rounding.
+// Moments R0, R1, R2 of the Toeplitz Gram (FP64) and e_t = d_t - d_0.
 struct TeamMoments {
-  double d[32];
+  double e[32];
   double2 r0[32];
-  float4 r12[32];
-  float2 r3[32];
+  double2 r1[32];
+  double2 r2[32];
 };
 
 // right-hand sides parked in LDS during the factorisation (lane-major)
@@ -250,7 +256,9 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   const int n = P.n;
   const int C = P.C;
 
-  for (int k = lane; k < NMAX; k += 16) T.m.d[k] = k < n ? P.d[k] : 0.0;
+  // e_k = d_k - d_0 (exact in FP64); padded layers take e = 0 (d = d_0)
+  const double d0 = P.d[0];
+  for (int k = lane; k < NMAX; k += 16) T.m.e[k] = k < n ? P.d[k] - d0 : 0.0;
   team_sync();
 
   double wx, wy;
@@ -261,7 +269,7 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int k = lane + 16 * r;
-    dk[r] = k < n ? T.m.d[k] : 0.0;
+    dk[r] = k < n ? T.m.e[k] + d0 : 0.0;
     dt[r] = dk[r] * kPhaseTab;
 #pragma unroll
     for (int c = 0; c < CT; ++c) acc[r][c] = cd{0.0, 0.0};
@@ -271,18 +279,20 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
 
   // ---- 1-2: stream the views ----
   // Channels c >= C (CT > C) read channel C - 1; their sums are never stored.
-  const float2* bp = P.view_spec + f;
   const size_t F = (size_t)P.F;
   const int m = P.m;
-  // Positions (and, with APER, focus, radius and shape) are read through a
-  // lane-varying (zero) offset so that they travel as vector loads: a scalar
-  // load would share its wait counter with the LDS table reads and stall
-  // every one of them.
-  int vzero;
+  // The spectra and positions are read as buffer loads: a uniform base and
+  // offsets in SGPRs plus a 32-bit lane offset (bin f), so no 64-bit address
+  // arithmetic runs per lane.  Positions (and, with APER, focus, radius and
+  // shape) are read through a lane-varying (zero) offset so that they travel
+  // as vector loads: a scalar load would share its wait counter with the LDS
+  // table reads and stall every one of them.
+  unsigned vzero;
   asm volatile("v_mov_b32 %0, 0" : "=v"(vzero));
-  const float2* up = P.u + vzero;
-  const float* vp = P.views + vzero;
-  const float2* sp = P.shifts + vzero;
+  const unsigned foff = (unsigned)f * 8u;
+  const unsigned cstride = (unsigned)P.F * 8u;   // bytes between the channels of one view
+  const auto u_rsrc = buf_rsrc(P.u);
+  auto at = [](const void* base, unsigned off) -> const char* { return (const char*)base + off; };
   struct ViewIn {
     float2 u;
     float s, rho;
@@ -294,29 +304,40 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
       // the shifts of this lane's layers (padded layers read layer n - 1;
       // their entries are replaced by the identity block)
 #pragma unroll
-      for (int r = 0; r < R; ++r) v.sh[r] = sp[(size_t)j * n + min(lane + 16 * r, n - 1)];
+      for (int r = 0; r < R; ++r)
+        v.sh[r] = *(const float2*)at(P.shifts + (size_t)j * n, 8u * (unsigned)min(lane + 16 * r, n - 1));
     } else if constexpr (APER) {
-      const float* q = vp + 5 * (size_t)j;
+      const float* q = (const float*)at(P.views + 5 * (size_t)j, vzero);
       v.u = make_float2(q[0], q[1]);
       v.s = q[2];
       v.rho = q[3];
       v.shape = __float_as_int(q[4]);
     } else {
-      v.u = up[j];
+      v.u = buf_load_f2(u_rsrc, vzero, 8u * (unsigned)j);
     }
+    const auto b_rsrc = buf_rsrc(P.view_spec + (size_t)j * C * F);
 #pragma unroll
-    for (int c = 0; c < CT; ++c) b[c] = bp[((size_t)j * C + (c < C ? c : C - 1)) * F];
+    for (int c = 0; c < CT; ++c) b[c] = buf_load_f2(b_rsrc, foff, cstride * (unsigned)(c < C ? c : C - 1));
   };
   const double wn = sqrt(wx * wx + wy * wy);
-  cd m0[R], m1[R], m2[R], m3[R];
+  cd m0[R], m1[R], m2[R];
   if constexpr (TOEP) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) m0[r] = m1[r] = m2[r] = m3[r] = cd{0.0, 0.0};
+    for (int r = 0; r < R; ++r) m0[r] = m1[r] = m2[r] = cd{0.0, 0.0};
   } else {
+    // the Gram sums start from the off-diagonal bands of the layer
+    // regulariser (zero for the other regularisers)
+    const double b1 = P.reg == 1 ? -4.0 * P.lambda : 0.0;
+    const double b2 = P.reg == 1 ? P.lambda : 0.0;
     static_for<0, R>([&](auto RR) {
       constexpr int r = decltype(RR)::value;
-#pragma unroll
-      for (int k = 0; k < 16 * (r + 1); ++k) S.template at<r>(k) = cd{0.0, 0.0};
+      const int i = lane + 16 * r;
+      static_for<0, 16 * (r + 1)>([&](auto KK) {
+        constexpr int k = decltype(KK)::value;
+        double band = i - k == 1 ? b1 : 0.0;
+        band = i - k == 2 ? b2 : band;
+        S.template at<r>(k) = cd{band, 0.0};
+      });
     });
   }
   auto view = [&](const ViewIn& vj, const float2 (&bc)[CT]) {
@@ -353,7 +374,7 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
     if constexpr (TOEP) {
       pmax = fmax(pmax, fabs(p));
       const cd a0 = bcast16<0>(A[0]);
-      const double p2 = p * p, p3 = p2 * p;
+      const double p2 = p * p;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         const cd g = cmulc(a0, A[r]);
@@ -362,8 +383,6 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
         m1[r].im = fma(p, g.im, m1[r].im);
         m2[r].re = fma(p2, g.re, m2[r].re);
         m2[r].im = fma(p2, g.im, m2[r].im);
-        m3[r].re = fma(p3, g.re, m3[r].re);
-        m3[r].im = fma(p3, g.im, m3[r].im);
       }
     } else {
       static_for<0, NMAX>([&](auto KK) {
@@ -419,8 +438,10 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
 
   // ---- 3: regulariser (bands of lambda Gamma^H Gamma + eps I) ----
   // diagonal per row: VIEW2 lambda |w|^4 d_i^4, LAYER2 lambda (4 + [i > 0] +
-  // [i < n - 1]), L2 lambda; plus eps.  LAYER2 also has -4 lambda on the first
-  // and lambda on the second sub-diagonal (the same in every row).
+  // [i < n - 1]), L2 lambda; plus eps.  It is added to the pivot in step 4.
+  // LAYER2 also has -4 lambda on the first and lambda on the second
+  // sub-diagonal (the same in every row): in the Toeplitz path they join the
+  // moments R0_1 and R0_2, in the general path they start the Gram sums.
   double diag[R];
   {
     const double w2 = wx * wx + wy * wy;
@@ -440,70 +461,49 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
       diag[r] = g + P.eps;
     }
   }
+
   const double sub1 = P.reg == 1 ? -4.0 * P.lambda : 0.0;
   const double sub2 = P.reg == 1 ? P.lambda : 0.0;
-  // entry (i, k = i - t) of the padded lower triangle from the Gram value
-  auto entry = [&](int t, int i, double dg, double gre, double gim) -> cd {
-    const bool live = (t >= 0) & (i < n);
-    double band = t == 2 ? sub2 : 0.0;
-    band = t == 1 ? sub1 : band;
-    band = t == 0 ? dg : band;
-    const double pad = t == 0 ? 1.0 : 0.0;
-    const double re = live ? gre + band : pad;
-    const double im = live & (t != 0) ? gim : 0.0;
-    return cd{re, im};
-  };
-
   if constexpr (TOEP) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int t = lane + 16 * r;
-      T.m.r0[t] = make_double2(m0[r].re, m0[r].im);
-      T.m.r12[t] = make_float4((float)m1[r].re, (float)m1[r].im, (float)m2[r].re, (float)m2[r].im);
-      T.m.r3[t] = make_float2((float)m3[r].re, (float)m3[r].im);
+      double band = t == 1 ? sub1 : 0.0;
+      band = t == 2 ? sub2 : band;
+      T.m.r0[t] = make_double2(m0[r].re + band, m0[r].im);
+      T.m.r1[t] = make_double2(m1[r].re, m1[r].im);
+      T.m.r2[t] = make_double2(m2[r].re, m2[r].im);
     }
     team_sync();
-    const double d0 = T.m.d[0];
+    // Lower-triangle entry (i, k), t = i - k: M_{k,i} = R0_t + i th R1_t -
+    // th^2/2 R2_t with th = 2 pi [(d_i - d_k) - (d_t - d_0)] = 2 pi (e_i - e_k -
+    // e_t), and M_{i,k} = conj(M_{k,i}).  Entries above the diagonal (and in the
+    // padded rows) read some other moment: finite values that no live entry
+    // of L ever reads.
     static_for<0, R>([&](auto RR) {
       constexpr int r = decltype(RR)::value;
       const int i = lane + 16 * r;
-      const double di = dk[r];
+      const double ei = kTwoPi * T.m.e[i];
       static_for<0, 16 * (r + 1)>([&](auto KK) {
         constexpr int k = decltype(KK)::value;
-        const int t = i - k;
-        const int tc = t < 0 ? 0 : t;
-        const double2 q0 = T.m.r0[tc];
-        const float4 q12 = T.m.r12[tc];
-        const float2 q3 = T.m.r3[tc];
-        const double th = kTwoPi * ((di - T.m.d[k]) - (T.m.d[tc] - d0));
-        const double h2 = 0.5 * th * th;
-        const double h3 = h2 * th * (1.0 / 3.0);
-        // M_{k,i} = R0 + i th R1 - th^2/2 R2 - i th^3/6 R3;  M_{i,k} = conj(M_{k,i})
-        const double mre = q0.x - th * (double)q12.y - h2 * (double)q12.z + h3 * (double)q3.y;
-        const double mim = q0.y + th * (double)q12.x - h2 * (double)q12.w - h3 * (double)q3.x;
-        cd e = entry(t, i, diag[r], mre, -mim);
+        const int t = (i - k) & 31;
+        const double2 q0 = T.m.r0[t];
+        const double2 q1 = T.m.r1[t];
+        const double2 q2 = T.m.r2[t];
+        const double th = (ei - kTwoPi * T.m.e[k]) - kTwoPi * T.m.e[t];
+        const double h2 = (0.5 * th) * th;
+        const double mre = fma(-h2, q2.x, fma(-th, q1.y, q0.x));
+        const double mim = fma(-h2, q2.y, fma(th, q1.x, q0.y));
+        cd e = cd{mre, -mim};
         pin(e);
         S.template at<r>(k) = e;
       });
     });
     if (lane == 0 && P.status && kTwoPi * P.eta_max * pmax > 3e-4) atomicAdd(P.status, 1);
-  } else {
-    static_for<0, R>([&](auto RR) {
-      constexpr int r = decltype(RR)::value;
-      const int i = lane + 16 * r;
-      static_for<0, 16 * (r + 1)>([&](auto KK) {
-        constexpr int k = decltype(KK)::value;
-        const cd g = S.template at<r>(k);
-        cd e = entry(i - k, i, diag[r], g.re, g.im);
-        pin(e);
-        S.template at<r>(k) = e;
-      });
-    });
   }
-
   if constexpr (REGION) {
-    // dense part of the finite-region view regulariser (the diagonal is the
-    // one of the view regulariser, already in place); padded rows untouched
+    // dense part of the finite-region view regulariser (its diagonal is the
+    // one of the view regulariser, added at the pivots); padded rows untouched
     sched_fence();
     const double w2 = wx * wx + wy * wy;
     const double lw = P.lambda * w2 * w2;
@@ -514,7 +514,7 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
       const double ci = lw * dk[r] * dk[r];
       static_for<0, 16 * (r + 1)>([&](auto KK) {
         constexpr int k = decltype(KK)::value;
-        const double dkk = T.m.d[k];
+        const double dkk = P.d[k];
         const double dd = dk[r] - dkk;
         const double g = ci * dkk * dkk * (double)(sinc_pi(rx * dd) * sinc_pi(ry * dd));
         S.template at<r>(k).re += (k < i && i < n) ? g : 0.0;
@@ -538,14 +538,18 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   static_for<0, NMAX>([&](auto JJ) {
     constexpr int j = decltype(JJ)::value;
     constexpr int oj = j % 16, sj = j / 16;
-    double piv = bcast16<oj>(S.template at<sj>(j).re);
+    // the diagonal register holds the Gram part; the regulariser's diagonal
+    // joins here.  Padded rows (j >= n) take the pivot 1 and 1/L_jj = 0.
+    double piv = bcast16<oj>(S.template at<sj>(j).re + diag[sj]);
+    if (j >= n) piv = 1.0;
     const bool ok = piv > 0.0 && isfinite(piv);
     bad = bad || !ok;
     piv = ok ? piv : 1e-300;
     double y = __builtin_amdgcn_rsq(piv);
     y = y * fma(-0.5 * piv * y, y, 1.5);
     y = y * fma(-0.5 * piv * y, y, 1.5);
-    invd[sj] = lane == oj ? y : invd[sj];
+    const double yl = j < n ? y : 0.0;
+    invd[sj] = lane == oj ? yl : invd[sj];
     static_for<0, R>([&](auto RR) {
       constexpr int r = decltype(RR)::value;
       if constexpr (j < 16 * (r + 1)) S.template at<r>(j) = cscale(S.template at<r>(j), y);
@@ -562,14 +566,18 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   });
   if (bad && lane == 0 && P.status) atomicAdd(P.status, 1);
 
-  // strictly lower part only (the padded rows are already zero off the diagonal)
+  // keep the strictly lower part of the live rows.  The padded rows are
+  // cleared: with their pivots forced to 1, their block is no Cholesky factor
+  // and may even overflow, so it must not meet the (zero) padded unknowns in
+  // the substitutions.  A select, not a product, so that Inf and NaN vanish.
   static_for<0, R>([&](auto RR) {
     constexpr int r = decltype(RR)::value;
     const int i = lane + 16 * r;
+    const bool live = i < n;
     static_for<0, 16 * (r + 1)>([&](auto KK) {
       constexpr int k = decltype(KK)::value;
       const cd v = S.template at<r>(k);
-      S.template at<r>(k) = k < i ? v : cd{0.0, 0.0};
+      S.template at<r>(k) = (k < i) & live ? v : cd{0.0, 0.0};
     });
   });
 

@@ -103,13 +103,30 @@ __device__ __forceinline__ cd expi2pi(double r) {
   return z;
 }
 
+// ---- raw buffer loads ----------------------------------------------------------
+// A buffer descriptor holds a uniform base address (in SGPRs); a load adds a
+// 32-bit per-lane offset and a uniform 32-bit offset in hardware, so per-lane
+// 64-bit address arithmetic disappears from the VALU.  The descriptor allows
+// offsets below 2 GiB (num_records) with no stride; word 3 selects the 32-bit
+// data format that raw (untyped) accesses on CDNA expect.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ float2 buf_load_f2(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  return make_float2(__uint_as_float(v[0]), __uint_as_float(v[1]));
+}
+
 // ---- 16-lane team communication (one DPP row = one team) -------------------
 
-// Value of `v` in lane SRC of this lane's 16-lane row.
+// Value of `v` in lane SRC of this lane's 16-lane row (row_newbcast).  The
+// DPP move has no "old" operand (bound_ctrl), so the compiler needs no copy
+// of the source into the destination first; every source lane of a row is
+// active wherever these are used, so the result is the same.
 template <int SRC>
 __device__ __forceinline__ double bcast16(double v) {
   long long x = __double_as_longlong(v);
-  x = __builtin_amdgcn_update_dpp(x, x, 0x150 + SRC, 0xF, 0xF, false);
+  x = __builtin_amdgcn_mov_dpp(x, 0x150 + SRC, 0xF, 0xF, true);
   return __longlong_as_double(x);
 }
 template <int SRC>
@@ -123,7 +140,7 @@ __device__ __forceinline__ cd bcast16(cd v) {
 template <int CTRL>
 __device__ __forceinline__ double dpp_mov(double v) {
   long long x = __double_as_longlong(v);
-  x = __builtin_amdgcn_update_dpp(x, x, CTRL, 0xF, 0xF, false);
+  x = __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, true);
   return __longlong_as_double(x);
 }
 __device__ __forceinline__ double allreduce16(double v) {

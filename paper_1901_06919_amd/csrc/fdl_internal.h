@@ -70,7 +70,8 @@ struct CalibParams {
   const float2* view_spec;   // [m][C][F]
   const float2* u;           // [m]
   const float* d;            // [n]
-  const int* freq_idx;       // [Q] or null (all F bins)
+  const int* freq_idx;       // [Q] or null (all F bins); clamped into [0, F)
+  int* status = nullptr;     // device counter of out-of-range indices, or null
   double* partial;           // workspace [blocks][stride]
   double* loss;              // [1]
   double* grad_u;            // [m][2]

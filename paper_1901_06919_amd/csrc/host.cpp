@@ -191,8 +191,8 @@ size_t fdl_calib_workspace(int m, int n, int Q) {
 
 int fdl_calib_grad(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_dev, int m, int n, int C, int H,
                    int W, float lambda, float eps, int reg, int mode, const int32_t* freq_idx_dev, int Q,
-                   double* loss_dev, double* grad_u_dev, double* grad_d_dev, void* ws_dev, size_t ws_bytes,
-                   void* stream) {
+                   double* loss_dev, double* grad_u_dev, double* grad_d_dev, int32_t* status_dev, void* ws_dev,
+                   size_t ws_bytes, void* stream) {
   if (!view_spec_dev || !u_dev || !d_dev || !loss_dev || !grad_u_dev || !grad_d_dev || !ws_dev) return FDL_EINVAL;
   if (!(std::isfinite(lambda) && lambda >= 0.f) || !(std::isfinite(eps) && eps >= 0.f)) return FDL_EINVAL;
   if (reg < FDL_REG_VIEW2 || reg > FDL_REG_L2 || (mode != FDL_LOSS_FIT && mode != FDL_LOSS_LOO)) return FDL_EINVAL;
@@ -209,6 +209,7 @@ int fdl_calib_grad(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const floa
   P.u = reinterpret_cast<const float2*>(u_dev);
   P.d = d_dev;
   P.freq_idx = freq_idx_dev;
+  P.status = status_dev;
   P.partial = static_cast<double*>(ws_dev);
   P.loss = loss_dev;
   P.grad_u = grad_u_dev;
@@ -343,7 +344,8 @@ size_t fdl_calib_relaxed_workspace(int m, int n, int Q) {
 
 int fdl_calib_grad_relaxed(const fdl_c64* view_spec_dev, const fdl_f2* shifts_dev, int m, int n, int C, int H, int W,
                            float lambda, float eps, int reg, int mode, const int32_t* freq_idx_dev, int Q,
-                           double* loss_dev, double* grad_shifts_dev, void* ws_dev, size_t ws_bytes, void* stream) {
+                           double* loss_dev, double* grad_shifts_dev, int32_t* status_dev, void* ws_dev,
+                           size_t ws_bytes, void* stream) {
   if (!view_spec_dev || !shifts_dev || !loss_dev || !grad_shifts_dev || !ws_dev) return FDL_EINVAL;
   if (!(std::isfinite(lambda) && lambda >= 0.f) || !(std::isfinite(eps) && eps >= 0.f)) return FDL_EINVAL;
   if ((reg != FDL_REG_LAYER2 && reg != FDL_REG_L2) || (mode != FDL_LOSS_FIT && mode != FDL_LOSS_LOO))
@@ -362,6 +364,7 @@ int fdl_calib_grad_relaxed(const fdl_c64* view_spec_dev, const fdl_f2* shifts_de
   P.d = nullptr;
   P.shifts = reinterpret_cast<const float2*>(shifts_dev);
   P.freq_idx = freq_idx_dev;
+  P.status = status_dev;
   P.partial = static_cast<double*>(ws_dev);
   P.loss = loss_dev;
   P.grad_u = nullptr;

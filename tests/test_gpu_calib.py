@@ -180,3 +180,30 @@ def test_calibration_trajectory_first_steps():
         ed = rel(td.cpu().numpy(), d_o)
         print(f"  step {step}: rel u {eu:.2e} d {ed:.2e}")
         assert eu < 1e-4 and ed < 1e-4
+
+
+@pytest.mark.parametrize("relaxed", [False, True])
+def test_calib_out_of_range_indices_are_clamped_and_counted(relaxed):
+    """Indices outside [0, F) are clamped to the nearest end, counted in the
+    status word, and the outputs equal those of the clamped index set."""
+    m, n, C, H, W = 6, 5, 1, 8, 8
+    print(f"calib out-of-range indices relaxed={relaxed}", flush=True)
+    u, d, spec, F = _small(321, m, n, C, H, W)
+    raw = np.array([3, -7, F + 11, 5, F, -1, 9], dtype=np.int32)
+    clamped = np.clip(raw, 0, F - 1).astype(np.int32)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    lam, eps = 1e-2, 1e-3
+    if relaxed:
+        sh = dev((d[None, :, None] * u[:, None, :]).astype(np.float32))
+        a = fdl().calib_grad_relaxed(dev(spec), sh, H, W, lam, eps, O.REG_LAYER2, O.LOSS_LOO, dev(raw), status=st)
+        b = fdl().calib_grad_relaxed(dev(spec), sh, H, W, lam, eps, O.REG_LAYER2, O.LOSS_LOO, dev(clamped))
+    else:
+        a = fdl().calib_grad(dev(spec), dev(u), dev(d), H, W, lam, eps, O.REG_LAYER2, O.LOSS_LOO, dev(raw), status=st)
+        b = fdl().calib_grad(dev(spec), dev(u), dev(d), H, W, lam, eps, O.REG_LAYER2, O.LOSS_LOO, dev(clamped))
+    torch.cuda.synchronize()
+    print(f"  status {st.item()}", flush=True)
+    assert int(st.item()) == 4
+    for x, y in zip(a, b):
+        x = x.cpu().numpy()
+        assert np.all(np.isfinite(x))
+        assert np.array_equal(x, y.cpu().numpy())

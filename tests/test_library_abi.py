@@ -48,7 +48,7 @@ def test_host_side_validation_without_gpu():
     assert L.fdl_rfft2(fake, fake, 1, 7, 8, None) == -2           # H = 7 unsupported
     assert L.fdl_render(fake, fake, 33, 1, 8, 8, fake, 1, fake, None) == -2
     assert L.fdl_calib_grad(fake, fake, fake, 300, 4, 1, 8, 8, 0.01, 0.001, 1, 1, None, 0,
-                            fake, fake, fake, fake, 1 << 20, None) == -2
+                            fake, fake, fake, None, fake, 1 << 20, None) == -2
     assert L.fdl_calib_workspace(49, 16, 4096) == 2048 * (1 + 98 + 16) * 8
     assert L.fdl_fma64_probe(None, 1, 1, None) == -1
     assert L.fdl_construct_views(None, fake, d, 4, 4, 1, 8, 8, 0.01, 0.001, 0, fake, None, None) == -1
@@ -60,11 +60,11 @@ def test_host_side_validation_without_gpu():
     assert L.fdl_render_relaxed(fake, fake, 33, 1, 8, 8, 1, fake, None) == -2
     assert L.fdl_render_relaxed(fake, fake, 4, 1, 8, 8, 0, fake, None) == -2
     assert L.fdl_calib_grad_relaxed(fake, fake, 4, 4, 1, 8, 8, 0.01, 0.001, 0, 0, None, 0,
-                                    fake, fake, fake, 1 << 20, None) == -1
+                                    fake, fake, None, fake, 1 << 20, None) == -1
     assert L.fdl_calib_grad_relaxed(fake, fake, 300, 4, 1, 8, 8, 0.01, 0.001, 1, 0, None, 0,
-                                    fake, fake, fake, 1 << 20, None) == -2
+                                    fake, fake, None, fake, 1 << 20, None) == -2
     assert L.fdl_calib_grad_relaxed(fake, fake, 4, 4, 1, 8, 8, 0.01, 0.001, 1, 0, None, 0,
-                                    fake, fake, fake, 16, None) == -3
+                                    fake, fake, None, fake, 16, None) == -3
     assert L.fdl_calib_relaxed_workspace(49, 16, 4096) == 2048 * (1 + 2 * 49 * 16) * 8
     assert L.fdl_gd_step_relaxed(None, fake, 4, 4, 0.2, 1e-6, None) == -1
     # drawn apertures: odd image side, table size limits
