@@ -228,6 +228,23 @@ int fdl_calib_grad(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const floa
                    double* loss_dev, double* grad_u_dev, double* grad_d_dev,
                    int32_t* status_dev, void* ws_dev, size_t ws_bytes, void* stream);
 
+/* Allocation-free variant of fdl_calib_grad, for callers that cannot
+ * allocate device memory or pass a workspace (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation).  Same arguments,
+ * results (bit for bit), status and errors as fdl_calib_grad, without ws_dev
+ * and ws_bytes: the per-block partial sums live in a static 4 MiB array of
+ * the library on each GPU (allocated with the library, held until the process
+ * ends).  Sizes whose workspace, fdl_calib_workspace(m, n, Q), exceeds 4 MiB
+ * are rejected with FDL_ENOMEM before anything is enqueued (m = 49, n = 16
+ * needs 1.8 MiB at any Q; m = 256, n = 32 fits for Q <= 961).  Every call on
+ * one GPU uses that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * Calls nothing that allocates. */
+int fdl_calib_grad_noalloc(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_dev,
+                           int m, int n, int C, int H, int W, float lambda, float eps, int reg, int mode,
+                           const int32_t* freq_idx_dev, int Q, double* loss_dev, double* grad_u_dev,
+                           double* grad_d_dev, int32_t* status_dev, void* stream);
+
 /* The normalised gradient step of Sec. V-B on the device:
  *   u <- u - alpha grad_u / (eps_g + ||grad_u||^2),  d <- d - alpha grad_d / (eps_g + ||grad_d||^2)
  * (squared norms as printed; alpha = 0.2 in the paper).  Computed in FP64,

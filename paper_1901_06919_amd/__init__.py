@@ -70,6 +70,9 @@ def lib():
         L.fdl_calib_grad.restype = i32
         L.fdl_calib_grad.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, i32,
                                      vp, i32, vp, vp, vp, vp, vp, sz, vp]
+        L.fdl_calib_grad_noalloc.restype = i32
+        L.fdl_calib_grad_noalloc.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, i32,
+                                             vp, i32, vp, vp, vp, vp, vp]
         L.fdl_gd_step.restype = i32
         L.fdl_gd_step.argtypes = [vp, vp, vp, vp, i32, i32, f64, f64, vp]
     if hasattr(L, "fdl_batch_plan_create"):
@@ -284,6 +287,36 @@ def calib_grad(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int
     _call("fdl_calib_grad", view_spec.data_ptr(), u.data_ptr(), d.data_ptr(), m, n, C, H, W, float(lam),
           float(eps), int(reg), int(mode), fp, Q, loss.data_ptr(), gu.data_ptr(), gd.data_ptr(),
           _status_ptr(status), ws.data_ptr(), ws.numel(), _stream(view_spec))
+    return loss, gu, gd
+
+
+def calib_grad_noalloc(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int, W: int,
+                       lam: float, eps: float, reg: int, mode: int, freq_idx: Optional[torch.Tensor] = None,
+                       out: Tuple[torch.Tensor, torch.Tensor, torch.Tensor] = None,
+                       status: Optional[torch.Tensor] = None):
+    """fdl_calib_grad_noalloc: :func:`calib_grad` without a workspace; the
+    library keeps the partial sums in its static per-GPU array.  ``out`` =
+    (loss [1], grad_u [m,2], grad_d [n]) float64 tensors is required, so the
+    call allocates nothing."""
+    m, C = view_spec.shape[:2]
+    n = d.shape[0]
+    _check(view_spec, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
+    _check(u, torch.float32, (m, 2), "u")
+    _check(d, torch.float32, (n,), "d")
+    if out is None:
+        raise ValueError("calib_grad_noalloc needs caller-provided outputs")
+    loss, gu, gd = out
+    _check(loss, torch.float64, (1,), "loss")
+    _check(gu, torch.float64, (m, 2), "grad_u")
+    _check(gd, torch.float64, (n,), "grad_d")
+    if freq_idx is not None:
+        _check(freq_idx, torch.int32, None, "freq_idx")
+        Q, fp = freq_idx.numel(), freq_idx.data_ptr()
+    else:
+        Q, fp = H * (W // 2 + 1), 0
+    _call("fdl_calib_grad_noalloc", view_spec.data_ptr(), u.data_ptr(), d.data_ptr(), m, n, C, H, W, float(lam),
+          float(eps), int(reg), int(mode), fp, Q, loss.data_ptr(), gu.data_ptr(), gd.data_ptr(),
+          _status_ptr(status), _stream(view_spec))
     return loss, gu, gd
 
 

@@ -22,6 +22,8 @@
 //       over the frequency components; the sampled subset replaces the full sum).
 // Per-block partial sums are reduced in a fixed order by a second kernel, so
 // the result is bitwise reproducible.
+#include <mutex>
+
 #include "fdl_device.h"
 #include "fdl_internal.h"
 
@@ -434,11 +436,13 @@ template <bool RELAXED>
 static hipError_t launch_calib_t(const CalibParams& P, hipStream_t s) {
   const size_t lds = calib_lds_bytes(P.m, P.n, P.C, P.mode, RELAXED);
   const int nb = calib_blocks(P.Q, lds);
-  static size_t opted = 65536;   // per instantiation: the attribute is per kernel
-  if (lds > opted) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_calib<RELAXED>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds);
-    opted = lds;
+  // Dynamic LDS beyond 64 KiB needs the kernel attribute on the current
+  // device; it is set on every such launch (a host-side call, no stream
+  // work), so no process-wide state decides it for another device or thread.
+  if (lds > 65536) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_calib<RELAXED>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_calib<RELAXED>, dim3(nb), dim3(256), lds, s, P);
   hipError_t e = hipGetLastError();
@@ -449,6 +453,34 @@ static hipError_t launch_calib_t(const CalibParams& P, hipStream_t s) {
 
 hipError_t launch_calib(const CalibParams& P, hipStream_t s) {
   return P.shifts ? launch_calib_t<true>(P, s) : launch_calib_t<false>(P, s);
+}
+
+// Partial-sum buffer of the allocation-free calibration entry point: a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Every block of k_calib overwrites its whole row, so nothing needs clearing
+// between calls; calls that overlap in time on one GPU share it and race.
+static __device__ __align__(256) double scratch[kCalibScratchBytes / sizeof(double)];
+
+// Device address of `scratch` on the current device.  The name is only a
+// host-side stand-in for the array; its address on each device comes from
+// the runtime, looked up once per device (under a lock) and kept.
+hipError_t calib_scratch(double** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *out = addr[dev];
+  return hipSuccess;
 }
 
 // Sec. V-B update, u' = u - alpha grad_u / (eps + ||grad_u||^2) (same for d).

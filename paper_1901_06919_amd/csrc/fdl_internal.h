@@ -87,6 +87,10 @@ size_t calib_lds_bytes(int m, int n, int C, int mode, bool relaxed = false);
 constexpr int kCalibMaxBlocks = 2048;
 int calib_blocks(int Q, size_t lds_per_block);
 hipError_t launch_calib(const CalibParams& P, hipStream_t s);
+// Allocation-free calibration: size of the static partial-sum array and its
+// device address on the current device.
+constexpr size_t kCalibScratchBytes = size_t(4) << 20;
+hipError_t calib_scratch(double** out);
 hipError_t launch_gd_step(float2* u, float* d, const double* gu, const double* gd, int m, int n, double alpha,
                           double eps_g, hipStream_t s);
 hipError_t launch_irfft2(const FftParams& P, hipStream_t s);

@@ -90,7 +90,7 @@ const char* fdl_status_string(int code) {
   }
 }
 
-int fdl_version(void) { return 10000; }
+int fdl_version(void) { return 20000; }
 
 int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_host, int m, int n, int C,
                   int H, int W, float lambda, float eps, int reg, fdl_c64* layer_spec_dev, int32_t* status_dev,
@@ -219,6 +219,28 @@ int fdl_calib_grad(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const floa
   P.reg = reg; P.mode = mode; P.stride = 1 + 2 * m + n;
   trace("calib m n Q mode", m, n, Q, mode);
   return map_hip(fdl::launch_calib(P, reinterpret_cast<hipStream_t>(stream)));
+}
+
+int fdl_calib_grad_noalloc(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_dev, int m, int n,
+                           int C, int H, int W, float lambda, float eps, int reg, int mode, const int32_t* freq_idx_dev,
+                           int Q, double* loss_dev, double* grad_u_dev, double* grad_d_dev, int32_t* status_dev,
+                           void* stream) {
+  // same checks as fdl_calib_grad, then the partial sums go to the library's
+  // static array instead of a caller's workspace (no allocation of any kind)
+  if (!view_spec_dev || !u_dev || !d_dev || !loss_dev || !grad_u_dev || !grad_d_dev) return FDL_EINVAL;
+  if (m < 1 || m > 256 || n < 1 || n > FDL_MAX_LAYERS || C < 1 || C > FDL_MAX_CHANNELS) return FDL_ESHAPE;
+  if (H < 1 || W < 2 || (W & 1)) return FDL_ESHAPE;
+  const long long F = (long long)H * (W / 2 + 1);
+  if (F > (1LL << 30)) return FDL_ESHAPE;
+  const int Qeff = freq_idx_dev ? Q : (int)F;
+  if (Qeff < 1) return FDL_EINVAL;
+  const size_t need = fdl_calib_workspace(m, n, Qeff);
+  if (need > fdl::kCalibScratchBytes) return FDL_ENOMEM;
+  double* scratch_dev = nullptr;
+  const int e = map_hip(fdl::calib_scratch(&scratch_dev));
+  if (e != FDL_OK) return e;
+  return fdl_calib_grad(view_spec_dev, u_dev, d_dev, m, n, C, H, W, lambda, eps, reg, mode, freq_idx_dev, Q, loss_dev,
+                        grad_u_dev, grad_d_dev, status_dev, scratch_dev, fdl::kCalibScratchBytes, stream);
 }
 
 int fdl_gd_step(fdl_f2* u_dev, float* d_dev, const double* grad_u_dev, const double* grad_d_dev, int m, int n,
