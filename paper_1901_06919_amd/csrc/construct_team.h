@@ -385,11 +385,15 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
         m2[r].im = fma(p2, g.im, m2[r].im);
       }
     } else {
+      // row i accumulates conj(A_ji) A_jk, A_jk broadcast from its lane
       static_for<0, NMAX>([&](auto KK) {
         constexpr int k = decltype(KK)::value;
-        const cd Ak = bcast16<k % 16>(A[k / 16]);
-        if constexpr (k < 16) cfma_conj(S.template at<0>(k), A[0], Ak);
-        if constexpr (R > 1) cfma_conj(S.template at<1>(k), A[R - 1], Ak);
+        if constexpr (R > 1 && k < 16)
+          dpp_cfma_conj<k % 16>(S.template at<0>(k), A[0], S.template at<1>(k), A[1], A[0]);
+        else if constexpr (k < 16)
+          dpp_cfma_conj<k % 16>(S.template at<0>(k), A[0], A[0]);
+        else
+          dpp_cfma_conj<k % 16>(S.template at<1>(k), A[1], A[1]);
       });
     }
   };
@@ -554,13 +558,16 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
       constexpr int r = decltype(RR)::value;
       if constexpr (j < 16 * (r + 1)) S.template at<r>(j) = cscale(S.template at<r>(j), y);
     });
+    // trailing update M_ik -= L_ij conj(L_kj), L_kj broadcast from row k's lane
     static_for<j + 1, NMAX>([&](auto KK) {
       constexpr int k = decltype(KK)::value;
-      const cd Lkj = bcast16<k % 16>(S.template at<k / 16>(j));
-      static_for<0, R>([&](auto RR) {
-        constexpr int r = decltype(RR)::value;
-        if constexpr (k < 16 * (r + 1)) cfms_aconjb(S.template at<r>(k), S.template at<r>(j), Lkj);
-      });
+      const cd Lk = S.template at<k / 16>(j);
+      if constexpr (R > 1 && k < 16)
+        dpp_cfms_aconjb<k % 16>(S.template at<0>(k), S.template at<0>(j), S.template at<1>(k), S.template at<1>(j), Lk);
+      else if constexpr (k < 16)
+        dpp_cfms_aconjb<k % 16>(S.template at<0>(k), S.template at<0>(j), Lk);
+      else
+        dpp_cfms_aconjb<k % 16>(S.template at<1>(k), S.template at<1>(j), Lk);
     });
     sched_fence();
   });
@@ -598,19 +605,14 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
     constexpr int oj = j % 16, sj = j / 16;
 #pragma unroll
     for (int c = 0; c < CT; ++c) {
-      const cd yj = bcast16<oj>(cscale(acc[sj][c], invd[sj]));
-      static_for<0, R>([&](auto RR) {
-        constexpr int r = decltype(RR)::value;
-        if constexpr (j < 16 * (r + 1)) {
-          cd t = acc[r][c];
-          const cd l = S.template at<r>(j);
-          t.re = fma(-l.re, yj.re, t.re);
-          t.re = fma(l.im, yj.im, t.re);
-          t.im = fma(-l.re, yj.im, t.im);
-          t.im = fma(-l.im, yj.re, t.im);
-          acc[r][c] = t;
-        }
-      });
+      // y_j = acc_j / L_jj in its lane, broadcast into the updates
+      const cd yv = cscale(acc[sj][c], invd[sj]);
+      if constexpr (R > 1 && j < 16)
+        dpp_cfms<oj>(acc[0][c], S.template at<0>(j), acc[1][c], S.template at<1>(j), yv);
+      else if constexpr (j < 16)
+        dpp_cfms<oj>(acc[0][c], S.template at<0>(j), yv);
+      else
+        dpp_cfms<oj>(acc[1][c], S.template at<1>(j), yv);
     }
     sched_fence();
   });
@@ -646,13 +648,12 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
       constexpr int oi = i % 16, si = i / 16;
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
-        const cd xi = bcast16<oi>(cscale(acc[si][c], invd[si]));
-        if constexpr (i < 16) {
-          cfms_conja(acc[0][c], S.L0[i], xi);
-        } else {
-          cfms_conja(acc[0][c], S.L1[i - 16], xi);
-          cfms_conja(acc[1][c], S.L1[i], xi);
-        }
+        // x_i = acc_i / L_ii in its lane, broadcast into the updates
+        const cd xv = cscale(acc[si][c], invd[si]);
+        if constexpr (i < 16)
+          dpp_cfms_conja<oi>(acc[0][c], S.L0[i], xv);
+        else
+          dpp_cfms_conja<oi>(acc[0][c], S.L1[i - 16], acc[1][c], S.L1[i], xv);
       }
       sched_fence();
     });

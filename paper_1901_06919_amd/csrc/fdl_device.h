@@ -134,6 +134,120 @@ __device__ __forceinline__ cd bcast16(cd v) {
   return cd{bcast16<SRC>(v.re), bcast16<SRC>(v.im)};
 }
 
+// ---- fused broadcast multiply-adds: v_fmac_f64 with DPP row_newbcast -------
+// LLVM does not fold a DPP broadcast into an FP64 multiply-add, so these emit
+// v_fmac_f64_dpp directly: the first source is read from lane SRC of the
+// lane's 16-lane row, which saves the separate broadcast moves.  A DPP read
+// of a VGPR that a VALU instruction wrote needs two wait states, which the
+// compiler does not insert before inline assembly: every block starts with
+// s_nop 1, and no block writes a register it reads through DPP.  Each block
+// keeps the operation order of the plain complex helpers above (bit-identical
+// results).  `x` below is the broadcast operand.
+
+// acc -= a * conj(x)  [and acc1 -= a1 * conj(x)]
+template <int SRC>
+__device__ __forceinline__ void dpp_cfms_aconjb(cd& acc, cd a, cd x) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, -%2, %4 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %0, -%3, %5 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %1, -%2, %5 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %1, %3, %4 row_newbcast:%c6"
+      : "+v"(acc.re), "+v"(acc.im)
+      : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "n"(SRC));
+}
+template <int SRC>
+__device__ __forceinline__ void dpp_cfms_aconjb(cd& acc, cd a, cd& acc1, cd a1, cd x) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, -%4, %6 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %0, -%5, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, -%4, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, %5, %6 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, -%4, %8 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, -%5, %9 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %3, -%4, %9 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %3, %5, %8 row_newbcast:%c10"
+      : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
+      : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "v"(a1.re), "v"(a1.im), "n"(SRC));
+}
+
+// acc -= l * x  [and acc1 -= l1 * x]
+template <int SRC>
+__device__ __forceinline__ void dpp_cfms(cd& acc, cd l, cd x) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, -%2, %4 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %0, %3, %5 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %1, -%3, %4 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %1, -%2, %5 row_newbcast:%c6"
+      : "+v"(acc.re), "+v"(acc.im)
+      : "v"(x.re), "v"(x.im), "v"(l.re), "v"(l.im), "n"(SRC));
+}
+template <int SRC>
+__device__ __forceinline__ void dpp_cfms(cd& acc, cd l, cd& acc1, cd l1, cd x) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, -%4, %6 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %0, %5, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, -%5, %6 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, -%4, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, -%4, %8 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, %5, %9 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %3, -%5, %8 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %3, -%4, %9 row_newbcast:%c10"
+      : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
+      : "v"(x.re), "v"(x.im), "v"(l.re), "v"(l.im), "v"(l1.re), "v"(l1.im), "n"(SRC));
+}
+
+// acc -= conj(a) * x  [and acc1 -= conj(a1) * x]
+template <int SRC>
+__device__ __forceinline__ void dpp_cfms_conja(cd& acc, cd a, cd x) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, -%2, %4 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %0, -%3, %5 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %1, -%3, %4 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %1, %2, %5 row_newbcast:%c6"
+      : "+v"(acc.re), "+v"(acc.im)
+      : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "n"(SRC));
+}
+template <int SRC>
+__device__ __forceinline__ void dpp_cfms_conja(cd& acc, cd a, cd& acc1, cd a1, cd x) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, -%4, %6 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %0, -%5, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, -%5, %6 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, %4, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, -%4, %8 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, -%5, %9 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %3, -%5, %8 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %3, %4, %9 row_newbcast:%c10"
+      : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
+      : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "v"(a1.re), "v"(a1.im), "n"(SRC));
+}
+
+// acc += conj(a) * x  [and acc1 += conj(a1) * x]
+template <int SRC>
+__device__ __forceinline__ void dpp_cfma_conj(cd& acc, cd a, cd x) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %2, %4 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %0, %3, %5 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %1, %3, %4 row_newbcast:%c6\n\t"
+      "v_fmac_f64_dpp %1, -%2, %5 row_newbcast:%c6"
+      : "+v"(acc.re), "+v"(acc.im)
+      : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "n"(SRC));
+}
+template <int SRC>
+__device__ __forceinline__ void dpp_cfma_conj(cd& acc, cd a, cd& acc1, cd a1, cd x) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %4, %6 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %0, %5, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, %5, %6 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, -%4, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, %4, %8 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, %5, %9 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %3, %5, %8 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %3, -%4, %9 row_newbcast:%c10"
+      : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
+      : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "v"(a1.re), "v"(a1.im), "n"(SRC));
+}
+
 // Sum of `v` over the 16 lanes of the row, returned to every lane of the row.
 // Pair swap, quad swap, half-row mirror, row mirror: every lane adds the same
 // operands (in commuted order), so all 16 lanes hold bit-identical sums.
