@@ -152,12 +152,20 @@ __device__ __forceinline__ cd expi_tab(const double2* __restrict__ tab, double d
   return cd{fma(e.x, cx, -e.y * sx), fma(e.y, cx, e.x * sx)};
 }
 
-// Moments R0, R1, R2 of the Toeplitz Gram (FP64) and e_t = d_t - d_0.
+// e_t = d_t - d_0, then either the per-view records of one batch of the
+// Toeplitz view loop (at most 16 views x 6 entries) or, after the loop, the
+// moments R0, R1, R2 of the Toeplitz Gram (FP64).
+constexpr int kViewBatch = 16;
 struct TeamMoments {
   double e[32];
-  double2 r0[32];
-  double2 r1[32];
-  double2 r2[32];
+  union {
+    struct {
+      double2 r0[32];
+      double2 r1[32];
+      double2 r2[32];
+    };
+    double2 views[kViewBatch * 6];
+  };
 };
 
 // right-hand sides parked in LDS during the factorisation (lane-major)
@@ -170,6 +178,10 @@ struct TeamRhs {
 // LDS banks); only the R = 2 solver uses it, after the moments are dead.
 constexpr int kTrStride = 17;
 
+// One team's LDS.  The 16-byte pad after the union makes the per-team
+// stride an odd multiple of 16 bytes modulo the 256-byte bank period, so that
+// the four teams of a wave, reading the same offset of their own areas (the
+// view records), hit different banks.
 template <int R>
 union TeamLds {
   TeamMoments m;
@@ -371,33 +383,109 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
 #pragma unroll
       for (int r = 0; r < R; ++r) cfma_conj(acc[r][c], A[r], b);
     }
-    if constexpr (TOEP) {
-      pmax = fmax(pmax, fabs(p));
-      const cd a0 = bcast16<0>(A[0]);
-      const double p2 = p * p;
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const cd g = cmulc(a0, A[r]);
-        m0[r] = cadd(m0[r], g);
-        m1[r].re = fma(p, g.re, m1[r].re);
-        m1[r].im = fma(p, g.im, m1[r].im);
-        m2[r].re = fma(p2, g.re, m2[r].re);
-        m2[r].im = fma(p2, g.im, m2[r].im);
-      }
-    } else {
-      // row i accumulates conj(A_ji) A_jk, A_jk broadcast from its lane
-      static_for<0, NMAX>([&](auto KK) {
-        constexpr int k = decltype(KK)::value;
-        if constexpr (R > 1 && k < 16)
-          dpp_cfma_conj<k % 16>(S.template at<0>(k), A[0], S.template at<1>(k), A[1], A[0]);
-        else if constexpr (k < 16)
-          dpp_cfma_conj<k % 16>(S.template at<0>(k), A[0], A[0]);
-        else
-          dpp_cfma_conj<k % 16>(S.template at<1>(k), A[1], A[1]);
-      });
-    }
+    // row i accumulates conj(A_ji) A_jk, A_jk broadcast from its lane
+    static_for<0, NMAX>([&](auto KK) {
+      constexpr int k = decltype(KK)::value;
+      if constexpr (R > 1 && k < 16)
+        dpp_cfma_conj<k % 16>(S.template at<0>(k), A[0], S.template at<1>(k), A[1], A[0]);
+      else if constexpr (k < 16)
+        dpp_cfma_conj<k % 16>(S.template at<0>(k), A[0], A[0]);
+      else
+        dpp_cfma_conj<k % 16>(S.template at<1>(k), A[1], A[1]);
+    });
   };
-  if constexpr (APER) {
+  if constexpr (TOEP) {
+    // Toeplitz path.  Everything the lanes share about view j is formed once,
+    // by one lane, for a batch of 16 views and staged in LDS:
+    //   beta_jc = conj(A_j0) b_jc, Z_j = exp(2 pi i (d_16 - d_0) p_j), p_j, p_j^2.
+    // Lane l then needs only W_jt = conj(A_j0) A_jt for its rows t = l, l + 16:
+    //   W_jl = exp(2 pi i (d_l - d_0) p_j) from the table, and
+    //   W_j,l+16 = W_jl Z_j exp(i phi), phi = 2 pi eta_l p_j,
+    //   eta_l = (d_{l+16} - d_l) - (d_16 - d_0) (float rounding; |eta_l| <=
+    //   eta_max, so |phi| <= 3e-4 when the status check passes, and the series
+    //   1 - phi^2/2 + i phi is exact to 5e-12),
+    // and accumulates c_t += conj(W_jt) beta_jc (= conj(A_jt) b_jc) and the
+    // moments R_q,t += p_j^q W_jt.
+    double2* rec = T.m.views;
+    constexpr int RS = CT + 2;   // record: beta[CT], Z, (p, p^2)
+    const double dt0 = kPhaseTab * d0;
+    const double dtl = kPhaseTab * T.m.e[lane];
+    double c1 = 0.0, h1 = 0.0, dtz = 0.0;
+    if constexpr (R > 1) {
+      c1 = kTwoPi * ((T.m.e[lane + 16] - T.m.e[lane]) - T.m.e[16]);
+      h1 = -0.5 * c1 * c1;
+      dtz = kPhaseTab * T.m.e[16];
+    }
+    // raw inputs of the next batch (lane l: view j0 + l), loaded one batch ahead
+    float2 nu, nb[CT];
+    auto fetch = [&](int j0) {
+      const int jc = min(j0 + lane, m - 1);
+      nu = P.u[jc];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) nb[c] = P.view_spec[((size_t)jc * C + (c < C ? c : C - 1)) * F + f];
+    };
+    fetch(0);
+    for (int j0 = 0; j0 < m; j0 += kViewBatch) {
+      const float2 uu = nu;
+      float2 bb[CT];
+#pragma unroll
+      for (int c = 0; c < CT; ++c) bb[c] = nb[c];
+      if (j0 + kViewBatch < m) fetch(j0 + kViewBatch);
+      {
+        const bool valid = j0 + lane < m;
+        const double p = fma((double)uu.x, wx, (double)uu.y * wy);
+        const cd a0 = expi_tab(tab, dt0, p);
+        cd z = cd{1.0, 0.0};
+        if constexpr (R > 1) z = expi_tab(tab, dtz, p);
+        pmax = fmax(pmax, valid ? fabs(p) : 0.0);
+        team_sync();   // the previous batch's records have been read
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          const cd be = valid ? cmulc(a0, cd{(double)bb[c].x, (double)bb[c].y}) : cd{0.0, 0.0};
+          rec[lane * RS + c] = make_double2(be.re, be.im);
+        }
+        rec[lane * RS + CT] = make_double2(z.re, z.im);
+        rec[lane * RS + CT + 1] = make_double2(p, p * p);
+        team_sync();
+      }
+      const int nv = min(kViewBatch, m - j0);
+#pragma unroll 2
+      for (int v = 0; v < nv; ++v) {
+        const double2* q = rec + v * RS;
+        const double2 pp = q[CT + 1];
+        const double p = pp.x, p2 = pp.y;
+        cd W[R];
+        W[0] = expi_tab(tab, dtl, p);
+        if constexpr (R > 1) {
+          const double2 zz = q[CT];
+          const cd B = cmul(W[0], cd{zz.x, zz.y});
+          const double phi = c1 * p;
+          const double a = fma(h1, p2, 1.0);
+          W[1] = cd{fma(B.re, a, -B.im * phi), fma(B.im, a, B.re * phi)};
+        }
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+          const double2 be = q[c];
+#pragma unroll
+          for (int r = 0; r < R; ++r) cfma_conj(acc[r][c], W[r], cd{be.x, be.y});
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          m0[r] = cadd(m0[r], W[r]);
+          m1[r].re = fma(p, W[r].re, m1[r].re);
+          m1[r].im = fma(p, W[r].im, m1[r].im);
+          m2[r].re = fma(p2, W[r].re, m2[r].re);
+          m2[r].im = fma(p2, W[r].im, m2[r].im);
+        }
+      }
+    }
+    team_sync();
+    // largest |p_j| over the team (for the status check below)
+    pmax = fmax(pmax, dpp_mov<0xB1>(pmax));
+    pmax = fmax(pmax, dpp_mov<0x4E>(pmax));
+    pmax = fmax(pmax, dpp_mov<0x141>(pmax));
+    pmax = fmax(pmax, dpp_mov<0x140>(pmax));
+  } else if constexpr (APER) {
     // one view in flight: the aperture spectra already hold many registers
     ViewIn ua;
     float2 ba[CT];
