@@ -330,16 +330,18 @@ def systems(fdl, synth, dev, serve_seconds: float):
         for i in range(8):
             spec = torch.randn((81, 3, 512, 257), dtype=torch.complex64, device=dev, generator=g)
             pool.append(PoolEntry(spec, torch.from_numpy(lfb.u).to(dev), d, d.to(dev), 512, 512, 1e-3, 1e-3, 0))
-        for rate in (200.0, 1000.0):
-            reqs = synth.serving_requests(rate=rate, duration=serve_seconds, pool=8, seed=4)
-            for i, r in enumerate(reqs):
-                r.rid = i
-            res = {}
+        # the serving workload: 200 req/s for serve_seconds (60 s: about 12,000
+        # requests); a shorter stream at 1000 req/s shows the tail under load
+        for rate, seconds in ((200.0, serve_seconds), (1000.0, min(serve_seconds, 6.0))):
+            reqs = synth.serving_requests(rate=rate, duration=seconds, pool=8, seed=4)
+            res = {"requests": len(reqs), "seconds": seconds}
             for name, serial in (("continuous", False), ("serial_fifo", True)):
                 srv = FDLServer(pool, hbm_budget=2 << 30, max_render_batch=16, max_inflight=8, serial=serial)
-                srv.run(reqs[: max(1, len(reqs) // 10)])          # warm-up slice
-                res[name] = srv.run(reqs).summary()
-                del srv
+                srv.run(reqs[: max(1, len(reqs) // 20)])          # warm-up slice
+                res[name] = srv.run(reqs, timeout_s=seconds + 120.0).summary()
+                srv.close()
+                print(f"bench: serving {rate:.0f} req/s {name}: p50 {res[name].get('all_p50_ms', 0):.3f} ms "
+                      f"p99 {res[name].get('all_p99_ms', 0):.3f} ms", file=sys.stderr, flush=True)
             out["serving" if rate == 200.0 else f"serving_{int(rate)}rps"] = res
         del pool
         torch.cuda.empty_cache()
@@ -353,7 +355,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-systems", action="store_true")
-    ap.add_argument("--serve-seconds", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM counters)")
     args = ap.parse_args()

@@ -68,7 +68,8 @@ enum fdl_status {
   FDL_ENOMEM = -3,        /* workspace too small / device allocation failed */
   FDL_EHIP = -4,          /* HIP runtime or launch error */
   FDL_ENUMERIC = -5,      /* reserved for numerical failures reported on the host */
-  FDL_EUNSUPPORTED = -6   /* valid request this library version does not implement */
+  FDL_EUNSUPPORTED = -6,  /* valid request this library version does not implement */
+  FDL_ETIMEOUT = -7       /* a wait ended before the work it waited for */
 };
 
 enum fdl_reg {
@@ -153,6 +154,20 @@ int fdl_irfft2(fdl_c64* spec_dev, float* img_dev, int batch, int H, int W, void*
 int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_host,
                   int m, int n, int C, int H, int W, float lambda, float eps, int reg,
                   fdl_c64* layer_spec_dev, int32_t* status_dev, void* stream);
+
+/* fdl_construct restricted to the bins [bin_begin, bin_begin + bin_count) of
+ * the half spectrum (flat index f = ky (W/2+1) + kx): the same per-bin
+ * solves, written to the same places of layer_spec_dev; the other bins of
+ * the output are not touched.  The bins of a frequency are independent
+ * (Eq. LayerConstructionClosedForm holds per w), so a construction may be
+ * split into ranges: the request server splits long constructions so that
+ * renders can run between the pieces, and a multi-GPU construction would
+ * give each device its range.  FDL_EINVAL unless 0 <= bin_begin and
+ * 1 <= bin_count <= F - bin_begin; other arguments and errors as
+ * fdl_construct. */
+int fdl_construct_bins(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_host,
+                       int m, int n, int C, int H, int W, float lambda, float eps, int reg,
+                       int bin_begin, int bin_count, fdl_c64* layer_spec_dev, int32_t* status_dev, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Rendering (Sec. IV-B Eq. BsFourier; Sec. VI): for each request v and bin w
@@ -391,6 +406,109 @@ int fdl_calib_grad_relaxed(const fdl_c64* view_spec_dev, const fdl_f2* shifts_de
                            size_t ws_bytes, void* stream);
 int fdl_gd_step_relaxed(fdl_f2* shifts_dev, const double* grad_shifts_dev, int m, int n, double alpha, double eps_g,
                         void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Request server (systems pattern over the calls above; no single passage of
+ * the paper): construct and render requests against light fields kept
+ * resident on the device, served with continuous batching.
+ *
+ * Everything the server keeps on the device -- the resident layer spectra of
+ * every light field and the buffers of the work in flight -- lives in ONE
+ * device allocation of hbm_budget bytes made by fdl_server_create, so
+ * admission by HBM footprint is exact: a unit of work starts only when its
+ * buffer can be placed in it.  A construct re-solves the layers of its light
+ * field (fdl_construct) into a new buffer, which replaces the resident layers
+ * when it completes (renders already running keep reading the previous
+ * layers, which return to the pool when the last of them ends).  A render
+ * computes the view's spectrum (fdl_render) and image (fdl_irfft2); renders
+ * of one light field that have arrived are launched together (up to
+ * max_render_batch views).  A worker thread of the server retires finished
+ * work (event polling; the thread spins while work is in flight, so
+ * completion is observed within microseconds) and admits arrived requests in
+ * arrival order; a request that cannot start yet is skipped by later ones,
+ * except that after it has waited 50 ms nothing that arrived later starts
+ * before it.  Latency = completion seen by the worker - scheduled arrival.
+ * Streams run at the default priority (two for renders, one for constructs).
+ * serial = 1 gives the plain baseline: strict arrival order, one unit of
+ * work at a time on one stream, one view per render.
+ *
+ * Footprints: a construct needs n C H (W/2+1) 8 bytes; a rendered view needs
+ * its spectrum, image and record (C H (W/2+1) 8 + C H W 4 + 256 bytes,
+ * rounded to 256).  A request whose footprint exceeds the budget left beside
+ * the resident layers can never start: fdl_server_submit rejects it
+ * (FDL_ENOMEM, state FDL_REQ_REJECTED).  A request that cannot be placed
+ * while nothing is in flight (fragmented free space) is rejected too, so the
+ * server never waits forever.
+ * ------------------------------------------------------------------------- */
+typedef struct fdl_server fdl_server;
+
+enum fdl_req_kind { FDL_REQ_CONSTRUCT = 0, FDL_REQ_RENDER = 1 };
+enum fdl_req_state { FDL_REQ_QUEUED = 0, FDL_REQ_RUNNING = 1, FDL_REQ_DONE = 2, FDL_REQ_REJECTED = 3 };
+
+typedef struct {
+  int32_t kind;          /* FDL_REQ_CONSTRUCT or FDL_REQ_RENDER */
+  int32_t lf;            /* light field id from fdl_server_add_lightfield */
+  fdl_view view;         /* render: position, focus, aperture (as fdl_render) */
+  float* image_dev;      /* render: [C][H][W] float32 device buffer of the caller that receives
+                          * the image, or NULL (rendered, not copied out) */
+  double t_arrival;      /* scheduled arrival on the server clock (seconds since
+                          * fdl_server_create; fdl_server_now), < 0: now.  Requests may be
+                          * submitted ahead of their arrival; they start no earlier. */
+} fdl_request;
+
+typedef struct {
+  int64_t submitted, completed, rejected;
+  int64_t count[3];               /* completed: all, construct, render */
+  double p50_ms[3], p99_ms[3], mean_ms[3];   /* latency percentiles (linear interpolation), same order */
+  int64_t render_batches;         /* render launches */
+  double mean_render_batch;       /* views per render launch */
+  double pool_high_water_bytes;   /* most of the budget ever in use (resident + in flight) */
+  double resident_bytes;          /* resident layers of all light fields */
+  double first_arrival_s;         /* server clock at the earliest arrival of a completed request */
+  double last_completion_s;       /* server clock at the last completion */
+} fdl_server_summary;
+
+/* Creates a server on the current device: allocates the hbm_budget pool,
+ * pinned staging and streams, and starts its worker thread.  1 <=
+ * max_render_batch <= 256, 1 <= max_inflight <= 64 (units of work in flight). */
+int fdl_server_create(size_t hbm_budget, int max_render_batch, int max_inflight, int serial, fdl_server** out);
+/* Registers a light field: its view spectra, positions and d (HOST array,
+ * copied) as fdl_construct takes them; the buffers of view_spec_dev and u_dev
+ * must stay valid while the server lives.  Places its layers in the pool and
+ * constructs them (blocking).  FDL_ENOMEM if they do not fit. */
+int fdl_server_add_lightfield(fdl_server* s, const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_host,
+                              int m, int n, int C, int H, int W, float lambda, float eps, int reg, int32_t* lf_out);
+/* Queues a request; *id_out identifies it (also when rejected: FDL_ENOMEM).
+ * FDL_EINVAL for an unknown kind or light field. */
+int fdl_server_submit(fdl_server* s, const fdl_request* req, int64_t* id_out);
+/* State of a request (fdl_req_state) and, once done, its latency in ms
+ * (else -1).  Returns the first device error the server met, if any. */
+int fdl_server_poll(fdl_server* s, int64_t id, int32_t* state, double* latency_ms);
+/* Blocks until every accepted request has completed (FDL_ETIMEOUT after
+ * timeout_s seconds). */
+int fdl_server_drain(fdl_server* s, double timeout_s);
+/* The server clock (seconds since creation). */
+int fdl_server_now(fdl_server* s, double* t_now);
+/* Device address of the current resident layers of a light field
+ * ([n][C][H][W/2+1] complex64, valid until the next construct of it ends). */
+int fdl_server_layers(fdl_server* s, int32_t lf, const fdl_c64** layer_spec_dev);
+int fdl_server_stats(fdl_server* s, fdl_server_summary* out);
+/* Serves every accepted request to completion, then frees the server. */
+int fdl_server_destroy(fdl_server* s);
+
+/* The server's scheduling policy on a simulated device, without the GPU (for
+ * host-side tests and capacity planning): n_lf light fields with the given
+ * layer and per-view footprints, fixed service times (a construct takes
+ * construct_s, a render of V views V render_s_per_view; streams as the
+ * server's, each running its work in order), requests submitted with their
+ * arrival times.  out[i]: final state, render launch index (or -1), admission
+ * and completion times (simulated seconds). */
+typedef struct { double t_arrival; int32_t kind; int32_t lf; } fdl_sim_request;
+typedef struct { int32_t state; int32_t batch; double t_admit; double t_done; } fdl_sim_result;
+int fdl_server_simulate(size_t hbm_budget, int max_render_batch, int max_inflight, int serial, int n_lf,
+                        const size_t* layer_bytes, const size_t* view_bytes, double construct_s,
+                        double render_s_per_view, const fdl_sim_request* reqs, int nreq, fdl_sim_result* out,
+                        fdl_server_summary* stats);
 
 /* ---------------------------------------------------------------------------
  * Measurement utility (not part of the method): enqueues `blocks` blocks of

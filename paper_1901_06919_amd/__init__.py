@@ -55,6 +55,8 @@ def lib():
     L.fdl_version.argtypes = []
     L.fdl_construct.restype = i32
     L.fdl_construct.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, vp, vp, vp]
+    L.fdl_construct_bins.restype = i32
+    L.fdl_construct_bins.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, i32, i32, vp, vp, vp]
     L.fdl_construct_views.restype = i32
     L.fdl_construct_views.argtypes = [vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, i32, vp, vp, vp]
     L.fdl_render.restype = i32
@@ -194,6 +196,23 @@ def construct(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int,
         sp = status.data_ptr()
     _call("fdl_construct", view_spec.data_ptr(), u.data_ptr(), d_host.data_ptr(), m, n, C, H, W,
           float(lam), float(eps), int(reg), out.data_ptr(), sp, _stream(view_spec))
+    return out
+
+
+def construct_bins(view_spec: torch.Tensor, u: torch.Tensor, d: torch.Tensor, H: int, W: int, lam: float,
+                   eps: float, reg: int, bin_begin: int, bin_count: int, out: torch.Tensor,
+                   status: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """fdl_construct_bins: the bins [bin_begin, bin_begin + bin_count) of
+    :func:`construct` written into ``out`` (the other bins untouched)."""
+    m, C = view_spec.shape[:2]
+    n = d.shape[0]
+    _check(view_spec, torch.complex64, (m, C, H, W // 2 + 1), "view_spec")
+    _check(u, torch.float32, (m, 2), "u")
+    _check(out, torch.complex64, (n, C, H, W // 2 + 1), "out")
+    d_host = d.detach().to("cpu").to(torch.float32).contiguous()
+    _call("fdl_construct_bins", view_spec.data_ptr(), u.data_ptr(), d_host.data_ptr(), m, n, C, H, W,
+          float(lam), float(eps), int(reg), int(bin_begin), int(bin_count), out.data_ptr(), _status_ptr(status),
+          _stream(view_spec))
     return out
 
 

@@ -12,14 +12,14 @@ __global__ __launch_bounds__(256, TOEP ? 2 : 1) void k_construct(ConstructParams
   __syncthreads();
   const int lane = threadIdx.x & 15;
   const int team = threadIdx.x >> 4;
-  const int f = xcd_remap(blockIdx.x, gridDim.x) * 16 + team;
-  if (f >= P.F) return;
+  const int f = P.f_begin + xcd_remap(blockIdx.x, gridDim.x) * 16 + team;
+  if (f >= P.f_stop) return;
   team_solve<R, CT, TOEP>(P, s_team[team], s_tab, f, lane);
 }
 
 template <int CT, bool TOEP>
 static hipError_t go(const ConstructParams& P, hipStream_t s) {
-  const int blocks = (P.F + 15) / 16;
+  const int blocks = (P.f_stop - P.f_begin + 15) / 16;
   hipLaunchKernelGGL((k_construct<2, CT, TOEP>), dim3(blocks), dim3(256), 0, s, P);
   return hipGetLastError();
 }

@@ -21,6 +21,7 @@ struct ConstructParams {
   int toeplitz;              // 1: d is an arithmetic progression up to rounding
   double eta_max;            // max_k1<k2 |(d_k2-d_k1) - (d_{k2-k1}-d_0)|
   double region = 0.0;       // side of the camera-plane square of the finite-region regulariser
+  int f_begin = 0, f_stop = 0;   // bins solved by the plain kernels: [f_begin, f_stop)
   double d[32];
 };
 

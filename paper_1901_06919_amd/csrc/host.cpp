@@ -86,6 +86,7 @@ const char* fdl_status_string(int code) {
     case FDL_EHIP: return "HIP runtime error";
     case FDL_ENUMERIC: return "numerical failure";
     case FDL_EUNSUPPORTED: return "not supported by this library version";
+    case FDL_ETIMEOUT: return "timed out";
     default: return "unknown status";
   }
 }
@@ -95,6 +96,16 @@ int fdl_version(void) { return 20000; }
 int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_host, int m, int n, int C,
                   int H, int W, float lambda, float eps, int reg, fdl_c64* layer_spec_dev, int32_t* status_dev,
                   void* stream) {
+  if (H < 1 || W < 2 || (W & 1)) return FDL_ESHAPE;
+  const long long F = (long long)H * (W / 2 + 1);
+  if (F > (1LL << 30)) return FDL_ESHAPE;
+  return fdl_construct_bins(view_spec_dev, u_dev, d_host, m, n, C, H, W, lambda, eps, reg, 0, (int)F,
+                            layer_spec_dev, status_dev, stream);
+}
+
+int fdl_construct_bins(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float* d_host, int m, int n, int C,
+                       int H, int W, float lambda, float eps, int reg, int bin_begin, int bin_count,
+                       fdl_c64* layer_spec_dev, int32_t* status_dev, void* stream) {
   if (!view_spec_dev || !u_dev || !d_host || !layer_spec_dev) return FDL_EINVAL;
   if (!(std::isfinite(lambda) && lambda >= 0.f) || !(std::isfinite(eps) && eps >= 0.f)) return FDL_EINVAL;
   if (reg < FDL_REG_VIEW2 || reg > FDL_REG_L2) return FDL_EINVAL;
@@ -112,6 +123,9 @@ int fdl_construct(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const float
   P.status = status_dev;
   P.m = m; P.n = n; P.C = C; P.H = H; P.W = W; P.Wh = W / 2 + 1; P.F = (int)F;
   P.lambda = (double)lambda; P.eps = (double)eps; P.reg = reg;
+  if (bin_begin < 0 || bin_count < 1 || (long long)bin_begin + bin_count > F) return FDL_EINVAL;
+  P.f_begin = bin_begin;
+  P.f_stop = bin_begin + bin_count;
   fdl_host::classify(d_host, n, P);
   trace("construct m n C F", m, n, C, (int)F);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);

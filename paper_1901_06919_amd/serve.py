@@ -1,234 +1,266 @@
-"""Serving loop for mixed construct / render requests with continuous batching.
+"""Python driver of the library's request server (fdl_server_* in the C ABI).
 
-The server keeps a pool of light fields resident in HBM: their view spectra
-(inputs of construction) and their current layer spectra (inputs of
-rendering).  Requests arrive open-loop at their scheduled times:
+The server itself -- admission by HBM footprint from one budgeted device pool,
+continuous batching of renders per light field, the worker thread that
+retires finished work and launches arrived requests on its streams, and the
+latency bookkeeping -- lives in libfdl (csrc/serve.cpp, policy in
+csrc/serve_core.h).  This module only marshals arguments: it registers the
+light fields, submits a request stream with its scheduled arrival times (all
+ahead of time: the server starts each request no earlier than its arrival, so
+no Python runs between arrival and completion), waits for the server to
+drain, and reads back its statistics.
 
-* construct(lf): re-solve the layers of light field ``lf`` (fdl_construct)
-  into a fresh buffer on the construct stream; when it completes, the new
-  buffer becomes the resident layers of ``lf`` (renders already in flight keep
-  reading the old buffer, so results never mix two versions);
-* render(lf, view): one view (position, focus, aperture) of light field
-  ``lf`` -> fdl_render + fdl_irfft2 -> an image.
-
-Admission is by HBM footprint: each admitted unit of work reserves the bytes
-of the buffers it allocates (new layer buffer for a construct; spectrum +
-image per rendered view) against ``hbm_budget`` and releases them when its
-completion event fires; work that does not fit waits in the queue (the server
-never over-commits).  Continuous batching: every pass of the loop retires
-finished work, then admits whatever has arrived while memory and in-flight
-slots allow -- render requests for the same light field admitted together
-share one fdl_render pass over the layers (up to ``max_render_batch`` views)
--- so requests that arrive while others run join the device queues at once;
-renders and constructs run on different streams and overlap on the GPU.
-
-Latency = completion observed on the host - scheduled arrival time, so queueing
-delay is included (open loop, no coordinated omission).
+Requests are ``synth.Request`` objects (t_arrival, kind, lf, view); the
+latency of a request is its completion, as seen by the server's worker
+thread, minus its scheduled arrival (open loop, no coordinated omission).
 """
 from __future__ import annotations
 
-import collections
+import ctypes
 import dataclasses
-import time
 from typing import Dict, List, Optional
 
 import numpy as np
 import torch
 
-from . import construct, irfft2, render, view_records
+from . import FDLError, _check, lib
+
+REQ_CONSTRUCT = 0
+REQ_RENDER = 1
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_REJECTED = 0, 1, 2, 3
+
+
+class _View(ctypes.Structure):
+    _fields_ = [("u", ctypes.c_float), ("v", ctypes.c_float), ("focus", ctypes.c_float),
+                ("radius", ctypes.c_float), ("shape", ctypes.c_int32)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("lf", ctypes.c_int32), ("view", _View),
+                ("image_dev", ctypes.c_void_p), ("t_arrival", ctypes.c_double)]
+
+
+class _Summary(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("count", ctypes.c_int64 * 3), ("p50_ms", ctypes.c_double * 3), ("p99_ms", ctypes.c_double * 3),
+                ("mean_ms", ctypes.c_double * 3), ("render_batches", ctypes.c_int64),
+                ("mean_render_batch", ctypes.c_double), ("pool_high_water_bytes", ctypes.c_double),
+                ("resident_bytes", ctypes.c_double), ("first_arrival_s", ctypes.c_double),
+                ("last_completion_s", ctypes.c_double)]
+
+
+class _SimRequest(ctypes.Structure):
+    _fields_ = [("t_arrival", ctypes.c_double), ("kind", ctypes.c_int32), ("lf", ctypes.c_int32)]
+
+
+class _SimResult(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("batch", ctypes.c_int32), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+_declared = False
+
+
+def _L():
+    global _declared
+    L = lib()
+    if not _declared:
+        vp, i32, f32, f64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_double, ctypes.c_size_t
+        sigs = {
+            "fdl_server_create": [sz, i32, i32, i32, ctypes.POINTER(vp)],
+            "fdl_server_add_lightfield": [vp, vp, vp, vp, i32, i32, i32, i32, i32, f32, f32, i32,
+                                          ctypes.POINTER(i32)],
+            "fdl_server_submit": [vp, ctypes.POINTER(_Request), ctypes.POINTER(ctypes.c_int64)],
+            "fdl_server_poll": [vp, ctypes.c_int64, ctypes.POINTER(i32), ctypes.POINTER(f64)],
+            "fdl_server_drain": [vp, f64],
+            "fdl_server_now": [vp, ctypes.POINTER(f64)],
+            "fdl_server_layers": [vp, i32, ctypes.POINTER(vp)],
+            "fdl_server_stats": [vp, ctypes.POINTER(_Summary)],
+            "fdl_server_destroy": [vp],
+            "fdl_server_simulate": [sz, i32, i32, i32, i32, ctypes.POINTER(sz), ctypes.POINTER(sz), f64, f64,
+                                    ctypes.POINTER(_SimRequest), i32, ctypes.POINTER(_SimResult),
+                                    ctypes.POINTER(_Summary)],
+        }
+        for name, args in sigs.items():
+            fn = getattr(L, name)
+            fn.restype = i32
+            fn.argtypes = args
+        _declared = True
+    return L
+
+
+def _ok(fn: str, code: int):
+    if code != 0:
+        raise FDLError(fn, code)
+
+
+def _summary_dict(s: _Summary, budget: int) -> dict:
+    out = {"submitted": s.submitted, "completed": s.completed, "rejected": s.rejected,
+           "throughput_rps": s.completed / max(s.last_completion_s - s.first_arrival_s, 1e-9),
+           "max_reserved_MB": s.pool_high_water_bytes / 2 ** 20, "resident_MB": s.resident_bytes / 2 ** 20,
+           "budget_MB": budget / 2 ** 20, "render_batches": s.render_batches,
+           "mean_render_batch": s.mean_render_batch}
+    for k, name in enumerate(("all", "construct", "render")):
+        if s.count[k]:
+            out[f"{name}_p50_ms"] = s.p50_ms[k]
+            out[f"{name}_p99_ms"] = s.p99_ms[k]
+            out[f"{name}_mean_ms"] = s.mean_ms[k]
+            out[f"{name}_count"] = int(s.count[k])
+    return out
 
 
 @dataclasses.dataclass
 class PoolEntry:
     view_spec: torch.Tensor      # [m, C, H, W//2+1] complex64 (resident)
     u: torch.Tensor              # [m, 2] f32 device
-    d_host: torch.Tensor         # [n] f32 host (construct takes disparities by value)
-    d_dev: torch.Tensor          # [n] f32 device (render reads them on the device)
+    d_host: torch.Tensor         # [n] f32 host
+    d_dev: torch.Tensor          # [n] f32 device (for checks that render outside the server)
     H: int
     W: int
     lam: float
     eps: float
     reg: int
-    layers: Optional[torch.Tensor] = None   # resident layer spectra
-
-
-@dataclasses.dataclass
-class Work:
-    kind: str
-    reqs: list
-    event: torch.cuda.Event
-    bytes: int
-    lf: int
-    outputs: object
-    slot: int = -1               # pinned staging slot of the view parameters
 
 
 @dataclasses.dataclass
 class ServeStats:
     completed: int
-    duration_s: float
-    latency_ms: Dict[str, np.ndarray]
+    rejected: int
+    latency_ms: np.ndarray       # per completed request, in submission order
+    summary_dict: dict
     max_reserved_bytes: int
     hbm_budget: int
-    admitted_batches: int
     mean_render_batch: float
 
     def summary(self) -> dict:
-        out = {"completed": self.completed, "throughput_rps": self.completed / max(self.duration_s, 1e-9),
-               "max_reserved_MB": self.max_reserved_bytes / 2 ** 20, "budget_MB": self.hbm_budget / 2 ** 20,
-               "mean_render_batch": self.mean_render_batch}
-        for k, v in self.latency_ms.items():
-            if len(v):
-                out[f"{k}_p50_ms"] = float(np.percentile(v, 50))
-                out[f"{k}_p99_ms"] = float(np.percentile(v, 99))
-                out[f"{k}_count"] = int(len(v))
-        return out
+        return dict(self.summary_dict)
 
 
 class FDLServer:
+    """Handle of one library server.  ``serial=True`` is the plain baseline
+    (arrival order, one unit of work at a time on one stream, one view per
+    render)."""
+
     def __init__(self, pool: List[PoolEntry], hbm_budget: int = 4 << 30, max_render_batch: int = 16,
                  max_inflight: int = 8, keep_outputs_every: int = 0, serial: bool = False):
-        """serial=True is the plain baseline: one request at a time, in arrival
-        order, on one stream (no batching, no overlap)."""
+        L = _L()
         self.pool = pool
         self.budget = int(hbm_budget)
-        self.max_render_batch = int(max_render_batch)
-        self.max_inflight = int(max_inflight)
         self.keep_every = int(keep_outputs_every)
-        self.dev = pool[0].view_spec.device
-        if serial:
-            self.max_render_batch = 1
-            self.max_inflight = 1
-            one = torch.cuda.Stream(device=self.dev)
-            self.render_streams = [one]
-            self.construct_stream = one
-        else:
-            self.render_streams = [torch.cuda.Stream(device=self.dev) for _ in range(2)]
-            self.construct_stream = torch.cuda.Stream(device=self.dev)
-        self._rr = 0
         self.kept: Dict[int, torch.Tensor] = {}
-        # view parameters travel through a ring of pinned host slots (freed when
-        # the work that copied them completes), so uploads never block the loop
-        nslots = self.max_inflight + 2
-        self._pinned = torch.empty((nslots, self.max_render_batch, 5), dtype=torch.float32, pin_memory=True)
-        self._dev_views = torch.empty((nslots, self.max_render_batch, 5), dtype=torch.float32, device=self.dev)
-        self._free_slots = list(range(nslots))
+        h = ctypes.c_void_p()
+        _ok("fdl_server_create", L.fdl_server_create(self.budget, int(max_render_batch), int(max_inflight),
+                                                      1 if serial else 0, ctypes.byref(h)))
+        self.h = h
+        self.lf_ids = []
+        self._d_host = []
         for e in pool:
-            if e.layers is None:
-                e.layers = construct(e.view_spec, e.u, e.d_host, e.H, e.W, e.lam, e.eps, e.reg)
-        torch.cuda.synchronize(self.dev)
+            m, C = e.view_spec.shape[:2]
+            n = e.d_host.shape[0]
+            _check(e.view_spec, torch.complex64, (m, C, e.H, e.W // 2 + 1), "view_spec")
+            _check(e.u, torch.float32, (m, 2), "u")
+            d = e.d_host.to(torch.float32).contiguous().cpu()
+            self._d_host.append(d)
+            lf = ctypes.c_int32()
+            _ok("fdl_server_add_lightfield",
+                L.fdl_server_add_lightfield(self.h, e.view_spec.data_ptr(), e.u.data_ptr(), d.data_ptr(), m, n, C,
+                                            e.H, e.W, float(e.lam), float(e.eps), int(e.reg), ctypes.byref(lf)))
+            self.lf_ids.append(lf.value)
 
-    # -- footprints -------------------------------------------------------------
-    def _layer_bytes(self, e: PoolEntry) -> int:
-        return e.layers.numel() * e.layers.element_size()
+    def now(self) -> float:
+        t = ctypes.c_double()
+        _ok("fdl_server_now", _L().fdl_server_now(self.h, ctypes.byref(t)))
+        return t.value
 
-    def _render_bytes(self, e: PoolEntry, V: int) -> int:
-        C = e.view_spec.shape[1]
-        return V * C * e.H * ((e.W // 2 + 1) * 8 + e.W * 4)
+    def run(self, requests, time_scale: float = 1.0, lead_s: float = 0.05, timeout_s: float = 600.0) -> ServeStats:
+        """Submit ``requests`` (t_arrival, kind, lf, view, and an integer
+        ``rid`` when outputs are kept) with arrivals ``lead_s`` after now,
+        wait until the server has served them, and return the statistics."""
+        L = _L()
+        t0 = self.now() + lead_s
+        ids = []
+        images = {}
+        for r in requests:
+            req = _Request()
+            req.kind = REQ_CONSTRUCT if r.kind == "construct" else REQ_RENDER
+            req.lf = self.lf_ids[r.lf]
+            v = r.view
+            req.view = _View(float(v[0]), float(v[1]), float(v[2]), float(v[3]), int(round(float(v[4]))))
+            img = None
+            if req.kind == REQ_RENDER and self.keep_every and getattr(r, "rid", -1) % self.keep_every == 0:
+                e = self.pool[r.lf]
+                img = torch.empty((e.view_spec.shape[1], e.H, e.W), dtype=torch.float32, device=e.view_spec.device)
+                images[r.rid] = img
+            req.image_dev = img.data_ptr() if img is not None else None
+            req.t_arrival = t0 + r.t_arrival * time_scale
+            rid = ctypes.c_int64()
+            code = L.fdl_server_submit(self.h, ctypes.byref(req), ctypes.byref(rid))
+            if code not in (0, -3):   # FDL_ENOMEM: rejected, still counted
+                raise FDLError("fdl_server_submit", code)
+            ids.append(rid.value)
+        _ok("fdl_server_drain", L.fdl_server_drain(self.h, float(timeout_s)))
+        lat = []
+        for i in ids:
+            st = ctypes.c_int32()
+            ms = ctypes.c_double()
+            _ok("fdl_server_poll", L.fdl_server_poll(self.h, i, ctypes.byref(st), ctypes.byref(ms)))
+            if st.value == REQ_DONE:
+                lat.append(ms.value)
+        self.kept.update(images)
+        return self.stats(np.asarray(lat))
 
-    # -- work submission --------------------------------------------------------
-    def _submit_construct(self, req) -> Work:
-        e = self.pool[req.lf]
-        with torch.cuda.stream(self.construct_stream):
-            out = torch.empty_like(e.layers)
-            construct(e.view_spec, e.u, e.d_host, e.H, e.W, e.lam, e.eps, e.reg, out=out)
-            ev = torch.cuda.Event()
-            ev.record(self.construct_stream)
-        return Work("construct", [req], ev, self._layer_bytes(e), req.lf, out)
+    def stats(self, latency_ms: Optional[np.ndarray] = None) -> ServeStats:
+        s = _Summary()
+        _ok("fdl_server_stats", _L().fdl_server_stats(self.h, ctypes.byref(s)))
+        d = _summary_dict(s, self.budget)
+        return ServeStats(int(s.completed), int(s.rejected), latency_ms if latency_ms is not None else np.zeros(0), d,
+                          int(s.pool_high_water_bytes), self.budget, float(s.mean_render_batch))
 
-    def _submit_render(self, lf: int, reqs: list) -> Work:
+    def layers(self, lf: int) -> torch.Tensor:
+        """A copy of the current resident layers of light field ``lf``
+        ([n, C, H, W//2+1] complex64, on the device)."""
         e = self.pool[lf]
-        s = self.render_streams[self._rr % len(self.render_streams)]
-        self._rr += 1
-        layers = e.layers              # completed construct output (swapped in after its event fired)
-        slot = self._free_slots.pop()
-        V = len(reqs)
-        host = self._pinned[slot, :V]
-        host.copy_(torch.from_numpy(np.stack([r.view for r in reqs]).astype(np.float32)))
-        with torch.cuda.stream(s):
-            views = self._dev_views[slot, :V]
-            views.copy_(host, non_blocking=True)
-            rec = view_records(views)
-            spec = render(layers, e.d_dev, rec, e.H, e.W)
-            img = irfft2(spec, e.H, e.W)
-            ev = torch.cuda.Event()
-            ev.record(s)
-        layers.record_stream(s)
-        return Work("render", reqs, ev, self._render_bytes(e, V), lf, img, slot)
+        n, C = e.d_host.shape[0], e.view_spec.shape[1]
+        out = torch.empty((n, C, e.H, e.W // 2 + 1), dtype=torch.complex64, device=e.view_spec.device)
+        p = ctypes.c_void_p()
+        _ok("fdl_server_layers", _L().fdl_server_layers(self.h, self.lf_ids[lf], ctypes.byref(p)))
+        hip = ctypes.CDLL("libamdhip64.so")
+        hip.hipMemcpy.restype = ctypes.c_int
+        hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        torch.cuda.synchronize(out.device)
+        if hip.hipMemcpy(out.data_ptr(), p, out.numel() * 8, 3) != 0:   # device to device
+            raise RuntimeError("hipMemcpy of the resident layers failed")
+        return out
 
-    # -- main loop --------------------------------------------------------------
-    def run(self, requests, time_scale: float = 1.0) -> ServeStats:
-        """Serve ``requests`` (objects with t_arrival, kind, lf, view, and an
-        integer ``rid``) in real time; returns latency statistics."""
-        pending = collections.deque(sorted(requests, key=lambda r: r.t_arrival))
-        queue: collections.deque = collections.deque()
-        inflight: List[Work] = []
-        reserved = 0
-        max_reserved = 0
-        lat = {"render": [], "construct": [], "all": []}
-        batches = 0
-        rendered = 0
-        t0 = time.perf_counter()
-        while pending or queue or inflight:
-            now = time.perf_counter() - t0
-            while pending and pending[0].t_arrival * time_scale <= now:
-                queue.append(pending.popleft())
-            # retire finished work (in any order)
-            still = []
-            for w in inflight:
-                if w.event.query():
-                    done = time.perf_counter() - t0
-                    reserved -= w.bytes
-                    for r in w.reqs:
-                        ms = (done - r.t_arrival * time_scale) * 1e3
-                        lat[w.kind].append(ms)
-                        lat["all"].append(ms)
-                    if w.slot >= 0:
-                        self._free_slots.append(w.slot)
-                    if w.kind == "construct":
-                        self.pool[w.lf].layers = w.outputs        # swap in the new layers
-                    elif self.keep_every:
-                        for i, r in enumerate(w.reqs):
-                            if r.rid % self.keep_every == 0:
-                                self.kept[r.rid] = w.outputs[i].clone()
-                else:
-                    still.append(w)
-            inflight = still
-            # admit: constructs individually, renders grouped by light field
-            progressed = False
-            while queue and len(inflight) < self.max_inflight and self._free_slots:
-                head = queue[0]
-                if head.kind == "construct":
-                    need = self._layer_bytes(self.pool[head.lf])
-                    if reserved + need > self.budget:
-                        break
-                    queue.popleft()
-                    w = self._submit_construct(head)
-                else:
-                    lf = head.lf
-                    group = [r for r in queue if r.kind == "render" and r.lf == lf][: self.max_render_batch]
-                    need = self._render_bytes(self.pool[lf], len(group))
-                    while group and reserved + need > self.budget:
-                        group.pop()
-                        need = self._render_bytes(self.pool[lf], len(group))
-                    if not group:
-                        break
-                    ids = {id(r) for r in group}
-                    queue = collections.deque(r for r in queue if id(r) not in ids)
-                    w = self._submit_render(lf, group)
-                    batches += 1
-                    rendered += len(group)
-                reserved += w.bytes
-                max_reserved = max(max_reserved, reserved)
-                inflight.append(w)
-                progressed = True
-            if not progressed and inflight:
-                time.sleep(20e-6)
-            elif not progressed and not inflight and pending:
-                wait = pending[0].t_arrival * time_scale - (time.perf_counter() - t0)
-                if wait > 0:
-                    time.sleep(min(wait, 1e-3))
-        torch.cuda.synchronize(self.dev)
-        dur = time.perf_counter() - t0
-        return ServeStats(len(lat["all"]), dur, {k: np.asarray(v) for k, v in lat.items()}, max_reserved, self.budget,
-                          batches, rendered / max(batches, 1))
+    def close(self):
+        if self.h:
+            _ok("fdl_server_destroy", _L().fdl_server_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def simulate(budget: int, layer_bytes, view_bytes, requests, construct_s: float, render_s_per_view: float,
+             max_render_batch: int = 16, max_inflight: int = 8, serial: bool = False):
+    """The server's scheduling policy on a simulated device (no GPU):
+    ``requests`` = (t_arrival, kind, lf) tuples.  Returns (per-request
+    [state, batch, t_admit, t_done] rows, summary dict)."""
+    L = _L()
+    nlf = len(layer_bytes)
+    lb = (ctypes.c_size_t * nlf)(*[int(x) for x in layer_bytes])
+    vb = (ctypes.c_size_t * nlf)(*[int(x) for x in view_bytes])
+    reqs = (_SimRequest * max(1, len(requests)))()
+    for i, (t, kind, lf) in enumerate(requests):
+        reqs[i] = _SimRequest(float(t), int(kind), int(lf))
+    res = (_SimResult * max(1, len(requests)))()
+    s = _Summary()
+    _ok("fdl_server_simulate", L.fdl_server_simulate(int(budget), int(max_render_batch), int(max_inflight),
+                                                     1 if serial else 0, nlf, lb, vb, float(construct_s),
+                                                     float(render_s_per_view), reqs, len(requests), res,
+                                                     ctypes.byref(s)))
+    rows = [(res[i].state, res[i].batch, res[i].t_admit, res[i].t_done) for i in range(len(requests))]
+    return rows, _summary_dict(s, budget)

@@ -188,3 +188,26 @@ def test_construct_and_render_at_the_size_limits():
     err = O.rel_l2(got.cpu().numpy(), ref)
     print(f"  rel_l2 = {err:.3e}")
     assert err < TOL
+
+
+def test_construct_in_bin_ranges_equals_one_construction():
+    """fdl_construct_bins over three ranges (ragged ends, one crossing a row)
+    writes exactly the bits of one fdl_construct, and leaves other bins alone."""
+    rng = np.random.default_rng(77)
+    m, n, C, H, W = 9, 20, 3, 24, 30
+    u = rng.uniform(-2, 2, (m, 2)).astype(np.float32)
+    d = np.linspace(-2, 2, n).astype(np.float32)
+    spec = O.rfft2(rng.standard_normal((m, C, H, W))).astype(np.complex64)
+    F = H * (W // 2 + 1)
+    print(f"construct_bins m={m} n={n} C={C} F={F}", flush=True)
+    full = fdl().construct(dev(spec), dev(u), torch.from_numpy(d), H, W, 1e-2, 1e-3, O.REG_VIEW2)
+    out = torch.full_like(full, complex(7.0, -7.0))
+    for b0, cnt in ((0, 37), (37, 150), (187, F - 187)):
+        fdl().construct_bins(dev(spec), dev(u), torch.from_numpy(d), H, W, 1e-2, 1e-3, O.REG_VIEW2, b0, cnt, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, full)
+    part = torch.full_like(full, complex(7.0, -7.0))
+    fdl().construct_bins(dev(spec), dev(u), torch.from_numpy(d), H, W, 1e-2, 1e-3, O.REG_VIEW2, 40, 60, part)
+    flat, ref = part.reshape(n, C, F), full.reshape(n, C, F)
+    assert torch.equal(flat[:, :, 40:100], ref[:, :, 40:100])
+    assert bool((flat[:, :, :40] == complex(7.0, -7.0)).all()) and bool((flat[:, :, 100:] == complex(7.0, -7.0)).all())

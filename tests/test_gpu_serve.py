@@ -1,7 +1,8 @@
-"""Serving pattern: open-loop Poisson mix of construct and render requests
-with HBM-footprint admission and continuous batching; every checked result
-must equal the same request computed alone, and admission must never exceed
-the budget."""
+"""Serving pattern through the library's request server (fdl_server_*):
+an open-loop Poisson mix of construct and render requests with HBM-footprint
+admission and continuous batching; every checked result must equal the same
+request computed alone, the constructions in the mix must leave layers equal
+to a fresh construction, and admission must stay inside the budget."""
 import numpy as np
 import pytest
 import torch
@@ -12,7 +13,6 @@ pytestmark = pytest.mark.gpu
 
 
 def _pool(k, H=128, W=128, seed=40):
-    import paper_1901_06919_amd as fdl
     from paper_1901_06919_amd.serve import PoolEntry
     rng = np.random.default_rng(seed)
     pool = []
@@ -26,35 +26,57 @@ def _pool(k, H=128, W=128, seed=40):
     return pool
 
 
-def test_serving_results_equal_alone_and_admission_respects_budget():
+@pytest.mark.parametrize("serial", [False, True])
+def test_serving_results_equal_alone_and_admission_respects_budget(serial):
     import paper_1901_06919_amd as fdl
     from paper_1901_06919_amd.serve import FDLServer
+    print(f"serving mix through fdl_server_*: serial={serial}", flush=True)
     pool = _pool(3)
     reqs = synth.serving_requests(rate=400.0, duration=1.0, pool=3, seed=4)
     for i, r in enumerate(reqs):
         r.rid = i
-    # budget deliberately tight: a few renders or one construct at a time
+    # budget deliberately tight: the three resident layer sets, then room for
+    # one construction and a few rendered views at a time
     e = pool[0]
-    per_view = 3 * e.H * ((e.W // 2 + 1) * 8 + e.W * 4)
+    per_view = 256 * (-(-3 * e.H * (e.W // 2 + 1) * 8 // 256) + -(-3 * e.H * e.W * 4 // 256) + 1)
     layer_bytes = 30 * 3 * e.H * (e.W // 2 + 1) * 8
-    budget = layer_bytes + 6 * per_view
-    srv = FDLServer(pool, hbm_budget=budget, max_render_batch=8, max_inflight=6, keep_outputs_every=5)
+    budget = 4 * layer_bytes + 6 * per_view
+    srv = FDLServer(pool, hbm_budget=budget, max_render_batch=8, max_inflight=6, keep_outputs_every=5,
+                    serial=serial)
     stats = srv.run(reqs)
     summ = stats.summary()
-    print(summ)
-    assert stats.completed == len(reqs)
+    print(summ, flush=True)
+    assert stats.completed == len(reqs) and stats.rejected == 0
     assert stats.max_reserved_bytes <= budget
-    assert stats.mean_render_batch >= 1.0
+    if not serial:
+        assert summ["render_batches"] < summ["render_count"]   # some renders shared a launch
     checked = 0
     for rid, img in srv.kept.items():
         r = reqs[rid]
         e = pool[r.lf]
-        alone = fdl.irfft2(fdl.render(e.layers, e.d_dev, torch.from_numpy(r.view[None].copy()).cuda(), e.H, e.W),
+        layers = srv.layers(r.lf)
+        alone = fdl.irfft2(fdl.render(layers, e.d_dev, torch.from_numpy(r.view[None].copy()).cuda(), e.H, e.W),
                            e.H, e.W)[0]
         assert torch.equal(alone, img), f"request {rid} differs alone vs in the mix"
         checked += 1
     assert checked > 10
-    # the resident layers still equal a fresh construction (constructs in the mix are exact)
-    for e in pool:
+    # the constructions in the mix left layers equal to a fresh construction
+    for i, e in enumerate(pool):
         fresh = fdl.construct(e.view_spec, e.u, e.d_host, e.H, e.W, e.lam, e.eps, e.reg)
-        assert torch.equal(fresh, e.layers)
+        assert torch.equal(fresh, srv.layers(i))
+    srv.close()
+
+
+def test_server_rejects_a_request_larger_than_the_budget():
+    from paper_1901_06919_amd.serve import FDLServer
+    print("serving: over-budget request rejected at submit", flush=True)
+    pool = _pool(1, H=64, W=64)
+    e = pool[0]
+    layer_bytes = 30 * 3 * e.H * (e.W // 2 + 1) * 8
+    # room for the resident layers and one rendered view, not for a second layer set
+    srv = FDLServer(pool, hbm_budget=layer_bytes + (1 << 20), max_render_batch=4, max_inflight=4)
+    reqs = [synth.Request(0.0, "construct", 0, np.zeros(5, np.float32)),
+            synth.Request(0.001, "render", 0, np.array([0.5, -0.5, 0.0, 1.0, 1.0], np.float32))]
+    stats = srv.run(reqs)
+    assert stats.rejected == 1 and stats.completed == 1
+    srv.close()

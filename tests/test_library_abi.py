@@ -73,6 +73,13 @@ def test_host_side_validation_without_gpu():
     assert L.fdl_aperture_table(None, 5, 2, fake, None) == -1
     assert L.fdl_render_tabulated(fake, fake, 4, 1, 8, 8, fake, 1, fake, 12, 5, fake, None) == -2
     assert L.fdl_render_tabulated(fake, fake, 4, 1, 8, 8, fake, 1, None, 10, 5, fake, None) == -1
+    # request server: argument checks before any device work
+    h = ctypes.c_void_p()
+    assert L.fdl_server_create(ctypes.c_size_t(0), 4, 4, 0, ctypes.byref(h)) == -1
+    assert L.fdl_server_create(ctypes.c_size_t(1 << 30), 0, 4, 0, ctypes.byref(h)) == -1
+    assert L.fdl_server_create(ctypes.c_size_t(1 << 30), 4, 65, 0, ctypes.byref(h)) == -1
+    assert L.fdl_server_submit(None, None, None) == -1
+    assert L.fdl_server_destroy(None) == -1
     # finite-region view regulariser: the region side must be finite and positive
     assert L.fdl_construct_region(fake, fake, d, 4, 4, 1, 8, 8, 0.01, 0.001, 0.0, fake, None, None) == -1
     assert L.fdl_construct_region(fake, fake, d, 4, 40, 1, 8, 8, 0.01, 0.001, 2.0, fake, None, None) == -2
