@@ -106,10 +106,16 @@ def achievable(fdl, dev):
     return {"hbm_copy_GBs": hbm, "fp64_fma_TFLOPs": flops[0] / t_fma / 1e12}
 
 
-def cpu_baseline(u, d):
-    """The FP64 oracle's construction (unchanged) on a bounded sample of bins of
-    the same 9x9 / 512^2 / 30-layer / 3-channel problem, split over worker
-    threads (numpy's LAPACK calls release the GIL; BLAS pinned to 1 thread)."""
+def cpu_baseline(views_img, u, d, lam, eps, reg, render_views, calib):
+    """The FP64 oracle (unchanged), timed on the host cores on the benchmark's
+    own inputs, stage by stage: forward DFT of the 243 view images, the
+    construction of all 131,584 bins (from the oracle's own spectra), the
+    disk-aperture render of 16 of the 81 views (from the oracle's layers)
+    and the leave-one-out calibration gradient on 256 of the 4096 sampled
+    bins of the calibration workload.  Work is split over worker threads
+    (numpy's FFT, LAPACK and ufuncs release the GIL; BLAS pinned to one
+    thread each); every stage runs once to warm up, then 3 times, and the
+    median is reported, scaled to the benchmark's units."""
     import concurrent.futures
 
     import numpy as np
@@ -117,42 +123,68 @@ def cpu_baseline(u, d):
 
     from oracle import fdl_oracle as O
 
-    H = W = 512
-    u = np.asarray(u, dtype=np.float64)
-    d = np.asarray(d, dtype=np.float64)
-    m, n, C = 81, 30, 3
+    m, C, H, W = views_img.shape
     F = H * (W // 2 + 1)
-    rng = np.random.default_rng(7)
-    nbins = F                      # one full construction of the workload
-    idx = np.arange(F)
-    spec = np.zeros((m, C, H, W // 2 + 1), dtype=np.complex64)
-    flat = spec.reshape(m, C, -1)
-    flat[:, :, idx] = (rng.standard_normal((m, C, nbins)) + 1j * rng.standard_normal((m, C, nbins))).astype(np.complex64)
     workers = max(1, min(16, os.cpu_count() or 1))
-    chunks = np.array_split(idx, workers * 4)
 
-    def run(ch):
-        return O.construct(spec, u, d, H, W, 1e-3, 1e-3, O.REG_VIEW2, freq_index=ch)
+    def med(fn):
+        fn()
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
 
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        with concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
-            list(ex.map(run, chunks))
-        dt = time.perf_counter() - t0
-        one = idx[:4096]                 # single-thread mode on the first 4096 bins
-        t1 = time.perf_counter()
-        run(one)
-        dt1 = time.perf_counter() - t1
+    with threadpool_limits(limits=1), concurrent.futures.ThreadPoolExecutor(max_workers=workers) as ex:
+        flat = views_img.reshape(m * C, H, W)
+        img_chunks = np.array_split(np.arange(m * C), workers)
+        spec = np.empty((m * C, H, W // 2 + 1), dtype=np.complex128)
+
+        def fft():
+            def one(ix):
+                spec[ix] = O.rfft2(flat[ix])
+            list(ex.map(one, img_chunks))
+
+        t_fft = med(fft)
+        spec4 = spec.reshape(m, C, H, W // 2 + 1)
+        bins = np.array_split(np.arange(F), workers * 4)
+        layers = np.empty((len(d), C, F), dtype=np.complex128)
+
+        def construct():
+            def one(ix):
+                layers[:, :, ix] = O.construct(spec4, u, d, H, W, lam, eps, reg, freq_index=ix)
+            list(ex.map(one, bins))
+
+        t_con = med(construct)
+        lay4 = layers.reshape(len(d), C, H, W // 2 + 1)
+        rv = render_views[:16]
+
+        def render():
+            list(ex.map(lambda v: O.render(lay4, d, rv[v:v + 1], H, W), range(rv.shape[0])))
+
+        t_ren = med(render)
+        (cs, cu, cd, cH, cW, clam, ceps, creg, cidx) = calib
+        sample = np.array_split(cidx[:256], workers)
+
+        def calib_grad():
+            list(ex.map(lambda ix: O.calib_loss_grad(cs, cu, cd, cH, cW, clam, ceps, creg, O.LOSS_LOO, ix), sample))
+
+        t_cal = med(calib_grad) * (cidx.shape[0] / 256.0)
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
             model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
     except OSError:
         pass
-    return {"value": nbins / dt, "unit": "bins/s", "cores": workers, "kind": "oracle",
-            "sample": f"FP64 oracle construct of {nbins} of the {F} bins (81 views, 30 layers, 3 channels), "
-                      f"{workers} threads, {dt:.1f} s; single thread on {one.size} bins, {dt1:.1f} s",
-            "single_thread_value": one.size / dt1, "host_cpus": os.cpu_count(), "cpu_model": model}
+    return {"value": F / t_con, "unit": "bins/s", "cores": workers, "kind": "oracle",
+            "sample": (f"FP64 oracle on the benchmark's inputs, {workers} threads, median of 3 after a warm-up: "
+                       f"rfft2 of {m * C} images {H}x{W} ({t_fft:.2f} s), construction of all {F} bins "
+                       f"({t_con:.2f} s), disk render of {rv.shape[0]} of the views ({t_ren:.2f} s), LOO gradient on "
+                       f"256 of {cidx.shape[0]} bins of the 7x7/256^2 calibration workload (scaled)"),
+            "stages": {"rfft2_images_per_s": m * C / t_fft, "construct_bins_per_s": F / t_con,
+                       "render_views_per_s": rv.shape[0] / t_ren, "calib_grad_steps_per_s": 1.0 / t_cal},
+            "host_cpus": os.cpu_count(), "cpu_model": model}
 
 
 def systems(fdl, synth, dev, serve_seconds: float):
@@ -167,12 +199,21 @@ def systems(fdl, synth, dev, serve_seconds: float):
     out = {}
     g = torch.Generator(device=dev).manual_seed(3)
     items = []
+    print("bench: generating the 64 uneven light fields", file=sys.stderr, flush=True)
     for i in range(64):
-        gsz, side, n = synth.uneven_light_field_shape(i)
-        u = torch.from_numpy(synth.centered_grid_positions(gsz)).to(dev)
+        # instance i of the uneven-light-field generator (seed 3000 + i): its
+        # views are rendered from its layers at its positions (untimed set-up)
+        lf = synth.uneven_light_field(i)
+        side, n = lf.H, lf.n
+        u = torch.from_numpy(lf.u).to(dev)
         m = u.shape[0]
-        spec = torch.randn((m, 1, side, side // 2 + 1), dtype=torch.complex64, device=dev, generator=g)
-        d = torch.linspace(-2.0, 2.0, n)
+        d = torch.from_numpy(lf.d)
+        pin = torch.zeros((m, 5), dtype=torch.float32)
+        pin[:, 0:2] = torch.from_numpy(lf.u)
+        lsp = fdl.rfft2(torch.from_numpy(lf.layers).to(dev))
+        img_i = fdl.irfft2(fdl.render(lsp, d.to(dev), fdl.view_records(pin.to(dev)), side, side), side, side)
+        spec = fdl.rfft2(img_i + torch.from_numpy(lf.noise).to(dev))
+        del lsp, img_i
         items.append(dict(view_spec=spec, u=u, d=d.to(dev), d_host=d, H=side, W=side, lam=1e-2, eps=1e-3, reg=0,
                           out=torch.empty((n, 1, side, side // 2 + 1), dtype=torch.complex64, device=dev)))
     bins = sum(it["H"] * (it["W"] // 2 + 1) for it in items)
@@ -547,11 +588,74 @@ def main():
                               "regulariser over the camera-plane square of side 8", "ms": t_reg,
                   "bins_per_s": F / (t_reg * 1e-3)}
 
+    # the small configuration (5x5 views, 128^2, 1 channel, 8 layers, 16 pinhole
+    # renders): the whole path as plain launches and replayed from a HIP graph
+    lf1 = synth.lf_5x5_128()
+    H1, W1 = lf1.H, lf1.W
+    u1 = torch.from_numpy(lf1.u).to(dev)
+    d1h = torch.from_numpy(lf1.d).clone()
+    d1 = d1h.to(dev)
+    p1 = torch.zeros((lf1.m, 5), dtype=torch.float32)
+    p1[:, 0:2] = torch.from_numpy(lf1.u)
+    l1 = fdl.rfft2(torch.from_numpy(lf1.layers).to(dev))
+    img1 = fdl.irfft2(fdl.render(l1, d1, fdl.view_records(p1.to(dev)), H1, W1), H1, W1) + \
+        torch.from_numpy(lf1.noise).to(dev)
+    r1 = fdl.view_records(torch.from_numpy(lf1.views).to(dev))
+    V1 = int(r1.shape[0])
+    spec1 = torch.empty((lf1.m, lf1.C, H1, W1 // 2 + 1), dtype=torch.complex64, device=dev)
+    lay1 = torch.empty((lf1.n, lf1.C, H1, W1 // 2 + 1), dtype=torch.complex64, device=dev)
+    rsp1 = torch.empty((V1, lf1.C, H1, W1 // 2 + 1), dtype=torch.complex64, device=dev)
+    out1 = torch.empty((V1, lf1.C, H1, W1), dtype=torch.float32, device=dev)
+
+    def small_step():
+        fdl.rfft2(img1, out=spec1)
+        fdl.construct(spec1, u1, d1h, H1, W1, lf1.lam, lf1.eps, lf1.reg, out=lay1)
+        fdl.render(lay1, d1, r1, H1, W1, out=rsp1)
+        fdl.irfft2(rsp1, H1, W1, out=out1)
+
+    def timed_ms(fn, reps=50):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    t_small = timed_ms(small_step)
+    g1 = torch.cuda.CUDAGraph()
+    s1 = torch.cuda.Stream(device=dev)
+    s1.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(s1):
+        with torch.cuda.graph(g1, stream=s1):
+            small_step()
+    torch.cuda.current_stream(dev).wait_stream(s1)
+    t_small_g = timed_ms(g1.replay)
+    e_s = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    fdl.rfft2(img1, out=spec1)
+    e_s[0].record()
+    for _ in range(20):
+        fdl.construct(spec1, u1, d1h, H1, W1, lf1.lam, lf1.eps, lf1.reg, out=lay1)
+    e_s[1].record()
+    torch.cuda.synchronize()
+    small_row = {"workload": "5x5 views, 128x128, 1 channel, 8 layers linspace(-2,2), 16 pinhole renders "
+                             "(rfft2, construct, render, irfft2)",
+                 "plain_ms": t_small, "graph_ms": t_small_g, "graph_speedup": t_small / t_small_g,
+                 "construct_us": e_s[0].elapsed_time(e_s[1]) / 20 * 1e3,
+                 "bins_per_s_graph": H1 * (W1 // 2 + 1) / (t_small_g * 1e-3)}
+    del g1, l1, img1, spec1, lay1, rsp1, out1
+
     drawn_row = {"workload": f"{V} views of 512x512 RGB, 30 layers, drawn hexagonal aperture {S_ap}x{S_ap} "
                              f"padded to {S_ap * pad_ap}^2, bilinear reads",
                  "table_ms": e[0].elapsed_time(e[1]) / 5, "render_ms": e[1].elapsed_time(e[2]) / 5,
                  "analytic_render_ms": e[2].elapsed_time(e[3]) / 5}
 
+    views_host = views.cpu().numpy() if not args.no_cpu_baseline else None
+    b5_host = b5.cpu().numpy().astype(np.complex128) if not args.no_cpu_baseline else None
+    lfc_u0, lfc_d0 = u5_0.astype(np.float64), d5_0.astype(np.float64)
+    subsets_host = subsets.cpu().numpy()
     sysres = None
     if not args.no_systems:
         del spec, lay, rend, img, views, b5
@@ -560,7 +664,16 @@ def main():
 
     base = None
     if not args.no_cpu_baseline:
-        base = cpu_baseline(lfb.u, lfb.d)
+        print("bench: timing the FP64 oracle on the host cores", file=sys.stderr, flush=True)
+        calib_in = (b5_host, lfc_u0, lfc_d0, lfc.H, lfc.W, lfc.lam, lfc.eps, lfc.reg, subsets_host[0])
+        base = cpu_baseline(views_host, lfb.u.astype(np.float64), lfb.d.astype(np.float64), lfb.lam, lfb.eps, lfb.reg,
+                            lfb.views.astype(np.float64), calib_in)
+        gpu_rates = {"rfft2_images_per_s": m * C / (stage_us["rfft2"] * 1e-6),
+                     "construct_bins_per_s": F / (stage_us["construct"] * 1e-6),
+                     "render_views_per_s": V / (stage_us["render"] * 1e-6),
+                     "calib_grad_steps_per_s": 1.0 / (stage_us["calib_grad"] * 1e-6)}
+        base["gpu_stages"] = gpu_rates
+        base["gpu_over_cpu"] = {k: gpu_rates[k] / base["stages"][k] for k in gpu_rates}
 
     out = {
         "metric": "layer-construction frequency solves/s",
@@ -585,9 +698,10 @@ def main():
         "construct_views": views_row,
         "drawn_aperture": drawn_row,
         "construct_region": region_row,
+        "small_config": small_row,
         "roofline": roof,
         "cpu_baseline": base,
-        "gpu_over_cpu_oracle": (F / (ms_per_step * 1e-3)) / base["value"] if base else None,
+        "construct_bins_per_s": F / (stage_us["construct"] * 1e-6),
     }
     if sysres is not None:
         out["batching"] = sysres.get("batching")
