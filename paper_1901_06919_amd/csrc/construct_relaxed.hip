@@ -8,7 +8,7 @@
 namespace fdl {
 
 template <int R, int CT>
-__global__ __launch_bounds__(256) void k_construct_relaxed(ConstructParams P) {
+__global__ __launch_bounds__(256, 2) void k_construct_relaxed(ConstructParams P) {
   __shared__ TeamLds<R> s_team[16];
   __shared__ double2 s_tab[kPhaseTab];
   fill_phase_table(s_tab);

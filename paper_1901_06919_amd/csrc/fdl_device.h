@@ -137,20 +137,25 @@ __device__ __forceinline__ cd bcast16(cd v) {
 // ---- fused broadcast multiply-adds: v_fmac_f64 with DPP row_newbcast -------
 // LLVM does not fold a DPP broadcast into an FP64 multiply-add, so these emit
 // v_fmac_f64_dpp directly: the first source is read from lane SRC of the
-// lane's 16-lane row, which saves the separate broadcast moves.  A DPP read
-// of a VGPR that a VALU instruction wrote needs two wait states, which the
-// compiler does not insert before inline assembly: every block starts with
-// s_nop 1, and no block writes a register it reads through DPP.  Each block
-// keeps the operation order of the plain complex helpers above (bit-identical
-// results).  `x` below is the broadcast operand.
+// lane's 16-lane row, which saves the separate broadcast moves.  A DPP
+// instruction needs two wait states after the write of ANY VGPR it reads --
+// the broadcast source, the other source and the accumulator alike -- and the
+// compiler inserts none for instructions inside inline assembly.  So every
+// block starts with s_nop 1 (for the compiler's writes just before it), and
+// inside a block the multiply-adds into one accumulator register are at least
+// three instructions apart: the two-accumulator blocks interleave their four
+// chains, the one-accumulator blocks put an s_nop 0 between the two halves.
+// Per accumulator register the operations keep the order of the plain complex
+// helpers above (bit-identical results).  `x` below is the broadcast operand.
 
 // acc -= a * conj(x)  [and acc1 -= a1 * conj(x)]
 template <int SRC>
 __device__ __forceinline__ void dpp_cfms_aconjb(cd& acc, cd a, cd x) {
   asm("s_nop 1\n\t"
       "v_fmac_f64_dpp %0, -%2, %4 row_newbcast:%c6\n\t"
-      "v_fmac_f64_dpp %0, -%3, %5 row_newbcast:%c6\n\t"
       "v_fmac_f64_dpp %1, -%2, %5 row_newbcast:%c6\n\t"
+      "s_nop 0\n\t"
+      "v_fmac_f64_dpp %0, -%3, %5 row_newbcast:%c6\n\t"
       "v_fmac_f64_dpp %1, %3, %4 row_newbcast:%c6"
       : "+v"(acc.re), "+v"(acc.im)
       : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "n"(SRC));
@@ -159,12 +164,12 @@ template <int SRC>
 __device__ __forceinline__ void dpp_cfms_aconjb(cd& acc, cd a, cd& acc1, cd a1, cd x) {
   asm("s_nop 1\n\t"
       "v_fmac_f64_dpp %0, -%4, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %0, -%5, %7 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %1, -%4, %7 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, %5, %6 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %2, -%4, %8 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, -%5, %9 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %3, -%4, %9 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %0, -%5, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, %5, %6 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, -%5, %9 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %3, %5, %8 row_newbcast:%c10"
       : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
       : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "v"(a1.re), "v"(a1.im), "n"(SRC));
@@ -175,8 +180,9 @@ template <int SRC>
 __device__ __forceinline__ void dpp_cfms(cd& acc, cd l, cd x) {
   asm("s_nop 1\n\t"
       "v_fmac_f64_dpp %0, -%2, %4 row_newbcast:%c6\n\t"
-      "v_fmac_f64_dpp %0, %3, %5 row_newbcast:%c6\n\t"
       "v_fmac_f64_dpp %1, -%3, %4 row_newbcast:%c6\n\t"
+      "s_nop 0\n\t"
+      "v_fmac_f64_dpp %0, %3, %5 row_newbcast:%c6\n\t"
       "v_fmac_f64_dpp %1, -%2, %5 row_newbcast:%c6"
       : "+v"(acc.re), "+v"(acc.im)
       : "v"(x.re), "v"(x.im), "v"(l.re), "v"(l.im), "n"(SRC));
@@ -185,12 +191,12 @@ template <int SRC>
 __device__ __forceinline__ void dpp_cfms(cd& acc, cd l, cd& acc1, cd l1, cd x) {
   asm("s_nop 1\n\t"
       "v_fmac_f64_dpp %0, -%4, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %0, %5, %7 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %1, -%5, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, -%4, %7 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %2, -%4, %8 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, %5, %9 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %3, -%5, %8 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %0, %5, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, -%4, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, %5, %9 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %3, -%4, %9 row_newbcast:%c10"
       : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
       : "v"(x.re), "v"(x.im), "v"(l.re), "v"(l.im), "v"(l1.re), "v"(l1.im), "n"(SRC));
@@ -201,8 +207,9 @@ template <int SRC>
 __device__ __forceinline__ void dpp_cfms_conja(cd& acc, cd a, cd x) {
   asm("s_nop 1\n\t"
       "v_fmac_f64_dpp %0, -%2, %4 row_newbcast:%c6\n\t"
-      "v_fmac_f64_dpp %0, -%3, %5 row_newbcast:%c6\n\t"
       "v_fmac_f64_dpp %1, -%3, %4 row_newbcast:%c6\n\t"
+      "s_nop 0\n\t"
+      "v_fmac_f64_dpp %0, -%3, %5 row_newbcast:%c6\n\t"
       "v_fmac_f64_dpp %1, %2, %5 row_newbcast:%c6"
       : "+v"(acc.re), "+v"(acc.im)
       : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "n"(SRC));
@@ -211,12 +218,12 @@ template <int SRC>
 __device__ __forceinline__ void dpp_cfms_conja(cd& acc, cd a, cd& acc1, cd a1, cd x) {
   asm("s_nop 1\n\t"
       "v_fmac_f64_dpp %0, -%4, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %0, -%5, %7 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %1, -%5, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, %4, %7 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %2, -%4, %8 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, -%5, %9 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %3, -%5, %8 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %0, -%5, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, %4, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, -%5, %9 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %3, %4, %9 row_newbcast:%c10"
       : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
       : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "v"(a1.re), "v"(a1.im), "n"(SRC));
@@ -227,8 +234,9 @@ template <int SRC>
 __device__ __forceinline__ void dpp_cfma_conj(cd& acc, cd a, cd x) {
   asm("s_nop 1\n\t"
       "v_fmac_f64_dpp %0, %2, %4 row_newbcast:%c6\n\t"
-      "v_fmac_f64_dpp %0, %3, %5 row_newbcast:%c6\n\t"
       "v_fmac_f64_dpp %1, %3, %4 row_newbcast:%c6\n\t"
+      "s_nop 0\n\t"
+      "v_fmac_f64_dpp %0, %3, %5 row_newbcast:%c6\n\t"
       "v_fmac_f64_dpp %1, -%2, %5 row_newbcast:%c6"
       : "+v"(acc.re), "+v"(acc.im)
       : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "n"(SRC));
@@ -237,12 +245,12 @@ template <int SRC>
 __device__ __forceinline__ void dpp_cfma_conj(cd& acc, cd a, cd& acc1, cd a1, cd x) {
   asm("s_nop 1\n\t"
       "v_fmac_f64_dpp %0, %4, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %0, %5, %7 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %1, %5, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, -%4, %7 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %2, %4, %8 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, %5, %9 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %3, %5, %8 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %0, %5, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %1, -%4, %7 row_newbcast:%c10\n\t"
+      "v_fmac_f64_dpp %2, %5, %9 row_newbcast:%c10\n\t"
       "v_fmac_f64_dpp %3, -%4, %9 row_newbcast:%c10"
       : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
       : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "v"(a1.re), "v"(a1.im), "n"(SRC));
