@@ -4,7 +4,7 @@
 
 namespace fdl {
 
-template <int R, int CT, bool TOEP>
+template <int R, int CT, bool TOEP, int NF>
 __global__ __launch_bounds__(256, TOEP ? 2 : 1) void k_construct(ConstructParams P) {
   __shared__ TeamLds<R> s_team[16];
   __shared__ double2 s_tab[kPhaseTab];
@@ -14,13 +14,18 @@ __global__ __launch_bounds__(256, TOEP ? 2 : 1) void k_construct(ConstructParams
   const int team = threadIdx.x >> 4;
   const int f = P.f_begin + xcd_remap(blockIdx.x, gridDim.x) * 16 + team;
   if (f >= P.f_stop) return;
-  team_solve<R, CT, TOEP>(P, s_team[team], s_tab, f, lane);
+  team_solve<R, CT, TOEP, false, false, false, NF>(P, s_team[team], s_tab, f, lane);
 }
 
+// Systems of up to 30 unknowns skip the last two (padded) rows and columns of
+// the factorisation and substitutions.
 template <int CT, bool TOEP>
 static hipError_t go(const ConstructParams& P, hipStream_t s) {
   const int blocks = (P.f_stop - P.f_begin + 15) / 16;
-  hipLaunchKernelGGL((k_construct<2, CT, TOEP>), dim3(blocks), dim3(256), 0, s, P);
+  if (P.n <= 30)
+    hipLaunchKernelGGL((k_construct<2, CT, TOEP, 30>), dim3(blocks), dim3(256), 0, s, P);
+  else
+    hipLaunchKernelGGL((k_construct<2, CT, TOEP, 32>), dim3(blocks), dim3(256), 0, s, P);
   return hipGetLastError();
 }
 

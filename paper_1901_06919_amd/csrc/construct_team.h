@@ -255,7 +255,7 @@ __device__ __forceinline__ void team_transpose(TeamRows<R>& S, double2* tr, int 
 // side P.region (Eq. GTG): the diagonal of the view regulariser plus the dense
 // off-diagonal part lambda |w|^4 d_i^2 d_k^2 sinc(r dd w_x) sinc(r dd w_y)
 // (P.reg must be 0).
-template <int R, int CT, bool TOEP, bool APER = false, bool SHIFTS = false, bool REGION = false>
+template <int R, int CT, bool TOEP, bool APER = false, bool SHIFTS = false, bool REGION = false, int NF = 16 * R>
 __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>& T, const double2* __restrict__ tab,
                                            int f, int lane) {
   static_assert(!(TOEP && APER), "apertures break the Toeplitz structure");
@@ -265,6 +265,9 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   // a branch on n: the padded unknowns have zero right-hand sides and solve
   // to zero without touching the others.
   constexpr int NMAX = 16 * R;
+  // Rows and columns >= NF (n <= NF <= NMAX) are never touched by the Gram
+  // sums, the factorisation or the substitutions: their unknowns are zero.
+  static_assert(NF > 16 * (R - 1) && NF <= NMAX, "NF must lie in the last row slot");
   const int n = P.n;
   const int C = P.C;
 
@@ -383,15 +386,19 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
 #pragma unroll
       for (int r = 0; r < R; ++r) cfma_conj(acc[r][c], A[r], b);
     }
-    // row i accumulates conj(A_ji) A_jk, A_jk broadcast from its lane
-    static_for<0, NMAX>([&](auto KK) {
+    // row i accumulates conj(A_ji) A_jk, A_jk broadcast from its lane.  Where
+    // only one row of the lane takes part (k >= 16, or R = 1), columns k and
+    // k + 1 share one block.
+    static_for<0, NF>([&](auto KK) {
       constexpr int k = decltype(KK)::value;
+      constexpr int r1 = R - 1, k1 = 16 * (R - 1);   // the single-row range starts at k1
       if constexpr (R > 1 && k < 16)
         dpp_cfma_conj<k % 16>(S.template at<0>(k), A[0], S.template at<1>(k), A[1], A[0]);
-      else if constexpr (k < 16)
-        dpp_cfma_conj<k % 16>(S.template at<0>(k), A[0], A[0]);
-      else
-        dpp_cfma_conj<k % 16>(S.template at<1>(k), A[1], A[1]);
+      else if constexpr (!SHIFTS && ((k - k1) & 1) == 0 && k + 1 < NF)
+        dpp_cfma_conj2<k % 16, (k + 1) % 16>(S.template at<r1>(k), A[r1], A[r1], S.template at<r1>(k + 1), A[r1],
+                                             A[r1]);
+      else if constexpr (SHIFTS || ((k - k1) & 1) == 0)
+        dpp_cfma_conj<k % 16>(S.template at<r1>(k), A[r1], A[r1]);
     });
   };
   if constexpr (TOEP) {
@@ -627,7 +634,7 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   double invd[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) invd[r] = 0.0;
-  static_for<0, NMAX>([&](auto JJ) {
+  static_for<0, NF>([&](auto JJ) {
     constexpr int j = decltype(JJ)::value;
     constexpr int oj = j % 16, sj = j / 16;
     // the diagonal register holds the Gram part; the regulariser's diagonal
@@ -647,15 +654,20 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
       if constexpr (j < 16 * (r + 1)) S.template at<r>(j) = cscale(S.template at<r>(j), y);
     });
     // trailing update M_ik -= L_ij conj(L_kj), L_kj broadcast from row k's lane
-    static_for<j + 1, NMAX>([&](auto KK) {
+    // (where only one row of the lane takes part, columns k and k + 1 share
+    // one block)
+    static_for<j + 1, NF>([&](auto KK) {
       constexpr int k = decltype(KK)::value;
+      constexpr int r1 = R - 1;
+      constexpr int k1 = j + 1 > 16 * (R - 1) ? j + 1 : 16 * (R - 1);   // first single-row column
       const cd Lk = S.template at<k / 16>(j);
       if constexpr (R > 1 && k < 16)
         dpp_cfms_aconjb<k % 16>(S.template at<0>(k), S.template at<0>(j), S.template at<1>(k), S.template at<1>(j), Lk);
-      else if constexpr (k < 16)
-        dpp_cfms_aconjb<k % 16>(S.template at<0>(k), S.template at<0>(j), Lk);
-      else
-        dpp_cfms_aconjb<k % 16>(S.template at<1>(k), S.template at<1>(j), Lk);
+      else if constexpr (((k - k1) & 1) == 0 && k + 1 < NF)
+        dpp_cfms_aconjb2<k % 16, (k + 1) % 16>(S.template at<r1>(k), S.template at<r1>(j), Lk,
+                                               S.template at<r1>(k + 1), S.template at<r1>(j), Lk);
+      else if constexpr (((k - k1) & 1) == 0)
+        dpp_cfms_aconjb<k % 16>(S.template at<r1>(k), S.template at<r1>(j), Lk);
     });
     sched_fence();
   });
@@ -688,19 +700,25 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   // acc_j keeps c_j minus the contributions of y_0..y_{j-1}; y_j = acc_j / L_jj
   // is broadcast from its lane and every row i > j subtracts L_ij y_j (the
   // zeroed diagonal and upper entries leave the other rows unchanged).
-  static_for<0, NMAX>([&](auto JJ) {
+  static_for<0, NF>([&](auto JJ) {
     constexpr int j = decltype(JJ)::value;
     constexpr int oj = j % 16, sj = j / 16;
+    // y_j = acc_j / L_jj in its lane, broadcast into the updates (row j's
+    // own sums do not change at this step: its coefficient L_jj was zeroed)
+    cd yv[CT];
 #pragma unroll
-    for (int c = 0; c < CT; ++c) {
-      // y_j = acc_j / L_jj in its lane, broadcast into the updates
-      const cd yv = cscale(acc[sj][c], invd[sj]);
-      if constexpr (R > 1 && j < 16)
-        dpp_cfms<oj>(acc[0][c], S.template at<0>(j), acc[1][c], S.template at<1>(j), yv);
-      else if constexpr (j < 16)
-        dpp_cfms<oj>(acc[0][c], S.template at<0>(j), yv);
-      else
-        dpp_cfms<oj>(acc[1][c], S.template at<1>(j), yv);
+    for (int c = 0; c < CT; ++c) yv[c] = cscale(acc[sj][c], invd[sj]);
+    if constexpr (R > 1 && j < 16) {
+#pragma unroll
+      for (int c = 0; c < CT; ++c)
+        dpp_cfms<oj>(acc[0][c], S.template at<0>(j), acc[1][c], S.template at<1>(j), yv[c]);
+    } else {
+      // one row of the lane takes part: two channels per block
+      constexpr int r = sj;
+#pragma unroll
+      for (int c = 0; c + 1 < CT; c += 2)
+        dpp_cfms2<oj, oj>(acc[r][c], S.template at<r>(j), yv[c], acc[r][c + 1], S.template at<r>(j), yv[c + 1]);
+      if constexpr (CT & 1) dpp_cfms<oj>(acc[r][CT - 1], S.template at<r>(j), yv[CT - 1]);
     }
     sched_fence();
   });
@@ -731,17 +749,23 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
     // column layout: x_i = acc_i / L_ii is broadcast and every row k < i
     // subtracts conj(L_ik) x_i; rows k >= i see zero coefficients
     team_transpose<R>(S, T.tr, lane);
-    static_for<0, NMAX>([&](auto II) {
-      constexpr int i = NMAX - 1 - decltype(II)::value;
+    static_for<0, NF>([&](auto II) {
+      constexpr int i = NF - 1 - decltype(II)::value;
       constexpr int oi = i % 16, si = i / 16;
+      // x_i = acc_i / L_ii in its lane, broadcast into the updates (row i's own
+      // sums do not change: its coefficient is zero)
+      cd xv[CT];
 #pragma unroll
-      for (int c = 0; c < CT; ++c) {
-        // x_i = acc_i / L_ii in its lane, broadcast into the updates
-        const cd xv = cscale(acc[si][c], invd[si]);
-        if constexpr (i < 16)
-          dpp_cfms_conja<oi>(acc[0][c], S.L0[i], xv);
-        else
-          dpp_cfms_conja<oi>(acc[0][c], S.L1[i - 16], acc[1][c], S.L1[i], xv);
+      for (int c = 0; c < CT; ++c) xv[c] = cscale(acc[si][c], invd[si]);
+      if constexpr (i < 16) {
+        // only the first row of the lane takes part: two channels per block
+#pragma unroll
+        for (int c = 0; c + 1 < CT; c += 2)
+          dpp_cfms_conja2<oi, oi>(acc[0][c], S.L0[i], xv[c], acc[0][c + 1], S.L0[i], xv[c + 1]);
+        if constexpr (CT & 1) dpp_cfms_conja<oi>(acc[0][CT - 1], S.L0[i], xv[CT - 1]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) dpp_cfms_conja<oi>(acc[0][c], S.L1[i - 16], acc[1][c], S.L1[i], xv[c]);
       }
       sched_fence();
     });

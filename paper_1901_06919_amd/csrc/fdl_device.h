@@ -148,7 +148,7 @@ __device__ __forceinline__ cd bcast16(cd v) {
 // Per accumulator register the operations keep the order of the plain complex
 // helpers above (bit-identical results).  `x` below is the broadcast operand.
 
-// acc -= a * conj(x)  [and acc1 -= a1 * conj(x)]
+// acc -= a * conj(x), x from lane SRC
 template <int SRC>
 __device__ __forceinline__ void dpp_cfms_aconjb(cd& acc, cd a, cd x) {
   asm("s_nop 1\n\t"
@@ -160,22 +160,30 @@ __device__ __forceinline__ void dpp_cfms_aconjb(cd& acc, cd a, cd x) {
       : "+v"(acc.re), "+v"(acc.im)
       : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "n"(SRC));
 }
+// two independent updates in one block: acc0 with (a0, x0 from lane S0)
+// and acc1 with (a1, x1 from lane S1)
+template <int S0, int S1>
+__device__ __forceinline__ void dpp_cfms_aconjb2(cd& acc0, cd a0, cd x0, cd& acc1, cd a1, cd x1) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, -%4, %8 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %1, -%4, %9 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %2, -%6, %10 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %3, -%6, %11 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %0, -%5, %9 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %1, %5, %8 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %2, -%7, %11 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %3, %7, %10 row_newbcast:%c13"
+      : "+v"(acc0.re), "+v"(acc0.im), "+v"(acc1.re), "+v"(acc1.im)
+      : "v"(x0.re), "v"(x0.im), "v"(x1.re), "v"(x1.im), "v"(a0.re), "v"(a0.im), "v"(a1.re), "v"(a1.im),
+        "n"(S0), "n"(S1));
+}
+// acc and acc1 with the same broadcast x
 template <int SRC>
 __device__ __forceinline__ void dpp_cfms_aconjb(cd& acc, cd a, cd& acc1, cd a1, cd x) {
-  asm("s_nop 1\n\t"
-      "v_fmac_f64_dpp %0, -%4, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, -%4, %7 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, -%4, %8 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %3, -%4, %9 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %0, -%5, %7 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, %5, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, -%5, %9 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %3, %5, %8 row_newbcast:%c10"
-      : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
-      : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "v"(a1.re), "v"(a1.im), "n"(SRC));
+  dpp_cfms_aconjb2<SRC, SRC>(acc, a, x, acc1, a1, x);
 }
 
-// acc -= l * x  [and acc1 -= l1 * x]
+// acc -= l * x, x from lane SRC
 template <int SRC>
 __device__ __forceinline__ void dpp_cfms(cd& acc, cd l, cd x) {
   asm("s_nop 1\n\t"
@@ -187,22 +195,30 @@ __device__ __forceinline__ void dpp_cfms(cd& acc, cd l, cd x) {
       : "+v"(acc.re), "+v"(acc.im)
       : "v"(x.re), "v"(x.im), "v"(l.re), "v"(l.im), "n"(SRC));
 }
+// two independent updates in one block: acc0 with (l0, x0 from lane S0)
+// and acc1 with (l1, x1 from lane S1)
+template <int S0, int S1>
+__device__ __forceinline__ void dpp_cfms2(cd& acc0, cd l0, cd x0, cd& acc1, cd l1, cd x1) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, -%4, %8 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %1, -%5, %8 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %2, -%6, %10 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %3, -%7, %10 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %0, %5, %9 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %1, -%4, %9 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %2, %7, %11 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %3, -%6, %11 row_newbcast:%c13"
+      : "+v"(acc0.re), "+v"(acc0.im), "+v"(acc1.re), "+v"(acc1.im)
+      : "v"(x0.re), "v"(x0.im), "v"(x1.re), "v"(x1.im), "v"(l0.re), "v"(l0.im), "v"(l1.re), "v"(l1.im),
+        "n"(S0), "n"(S1));
+}
+// acc and acc1 with the same broadcast x
 template <int SRC>
 __device__ __forceinline__ void dpp_cfms(cd& acc, cd l, cd& acc1, cd l1, cd x) {
-  asm("s_nop 1\n\t"
-      "v_fmac_f64_dpp %0, -%4, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, -%5, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, -%4, %8 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %3, -%5, %8 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %0, %5, %7 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, -%4, %7 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, %5, %9 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %3, -%4, %9 row_newbcast:%c10"
-      : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
-      : "v"(x.re), "v"(x.im), "v"(l.re), "v"(l.im), "v"(l1.re), "v"(l1.im), "n"(SRC));
+  dpp_cfms2<SRC, SRC>(acc, l, x, acc1, l1, x);
 }
 
-// acc -= conj(a) * x  [and acc1 -= conj(a1) * x]
+// acc -= conj(a) * x, x from lane SRC
 template <int SRC>
 __device__ __forceinline__ void dpp_cfms_conja(cd& acc, cd a, cd x) {
   asm("s_nop 1\n\t"
@@ -214,22 +230,30 @@ __device__ __forceinline__ void dpp_cfms_conja(cd& acc, cd a, cd x) {
       : "+v"(acc.re), "+v"(acc.im)
       : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "n"(SRC));
 }
+// two independent updates in one block: acc0 with (a0, x0 from lane S0)
+// and acc1 with (a1, x1 from lane S1)
+template <int S0, int S1>
+__device__ __forceinline__ void dpp_cfms_conja2(cd& acc0, cd a0, cd x0, cd& acc1, cd a1, cd x1) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, -%4, %8 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %1, -%5, %8 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %2, -%6, %10 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %3, -%7, %10 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %0, -%5, %9 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %1, %4, %9 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %2, -%7, %11 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %3, %6, %11 row_newbcast:%c13"
+      : "+v"(acc0.re), "+v"(acc0.im), "+v"(acc1.re), "+v"(acc1.im)
+      : "v"(x0.re), "v"(x0.im), "v"(x1.re), "v"(x1.im), "v"(a0.re), "v"(a0.im), "v"(a1.re), "v"(a1.im),
+        "n"(S0), "n"(S1));
+}
+// acc and acc1 with the same broadcast x
 template <int SRC>
 __device__ __forceinline__ void dpp_cfms_conja(cd& acc, cd a, cd& acc1, cd a1, cd x) {
-  asm("s_nop 1\n\t"
-      "v_fmac_f64_dpp %0, -%4, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, -%5, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, -%4, %8 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %3, -%5, %8 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %0, -%5, %7 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, %4, %7 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, -%5, %9 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %3, %4, %9 row_newbcast:%c10"
-      : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
-      : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "v"(a1.re), "v"(a1.im), "n"(SRC));
+  dpp_cfms_conja2<SRC, SRC>(acc, a, x, acc1, a1, x);
 }
 
-// acc += conj(a) * x  [and acc1 += conj(a1) * x]
+// acc += conj(a) * x, x from lane SRC
 template <int SRC>
 __device__ __forceinline__ void dpp_cfma_conj(cd& acc, cd a, cd x) {
   asm("s_nop 1\n\t"
@@ -241,19 +265,27 @@ __device__ __forceinline__ void dpp_cfma_conj(cd& acc, cd a, cd x) {
       : "+v"(acc.re), "+v"(acc.im)
       : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "n"(SRC));
 }
+// two independent updates in one block: acc0 with (a0, x0 from lane S0)
+// and acc1 with (a1, x1 from lane S1)
+template <int S0, int S1>
+__device__ __forceinline__ void dpp_cfma_conj2(cd& acc0, cd a0, cd x0, cd& acc1, cd a1, cd x1) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %4, %8 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %1, %5, %8 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %2, %6, %10 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %3, %7, %10 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %0, %5, %9 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %1, -%4, %9 row_newbcast:%c12\n\t"
+      "v_fmac_f64_dpp %2, %7, %11 row_newbcast:%c13\n\t"
+      "v_fmac_f64_dpp %3, -%6, %11 row_newbcast:%c13"
+      : "+v"(acc0.re), "+v"(acc0.im), "+v"(acc1.re), "+v"(acc1.im)
+      : "v"(x0.re), "v"(x0.im), "v"(x1.re), "v"(x1.im), "v"(a0.re), "v"(a0.im), "v"(a1.re), "v"(a1.im),
+        "n"(S0), "n"(S1));
+}
+// acc and acc1 with the same broadcast x
 template <int SRC>
 __device__ __forceinline__ void dpp_cfma_conj(cd& acc, cd a, cd& acc1, cd a1, cd x) {
-  asm("s_nop 1\n\t"
-      "v_fmac_f64_dpp %0, %4, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, %5, %6 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, %4, %8 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %3, %5, %8 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %0, %5, %7 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %1, -%4, %7 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %2, %5, %9 row_newbcast:%c10\n\t"
-      "v_fmac_f64_dpp %3, -%4, %9 row_newbcast:%c10"
-      : "+v"(acc.re), "+v"(acc.im), "+v"(acc1.re), "+v"(acc1.im)
-      : "v"(x.re), "v"(x.im), "v"(a.re), "v"(a.im), "v"(a1.re), "v"(a1.im), "n"(SRC));
+  dpp_cfma_conj2<SRC, SRC>(acc, a, x, acc1, a1, x);
 }
 
 // Sum of `v` over the 16 lanes of the row, returned to every lane of the row.
