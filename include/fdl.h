@@ -270,8 +270,9 @@ int fdl_gd_step(fdl_f2* u_dev, float* d_dev, const double* grad_u_dev, const dou
 /* ---------------------------------------------------------------------------
  * Batched construction of uneven light fields (same mathematics as
  * fdl_construct for each light field) in one launch per channel/disparity
- * class, or one launch per row-slot class, as the plan's mode selects (the
- * autotuner picks the mode that measures fastest on the plan's own data).
+ * class, or one launch per solved-row class within it, as the plan's mode
+ * selects (the autotuner picks the mode that measures fastest on the plan's
+ * own data).
  *
  * fdl_batch_plan_create reads a HOST array of B descriptors, validates them,
  * chooses the launch shape (defaults, or the autotuner's choice), and
@@ -293,17 +294,19 @@ typedef struct fdl_lf_desc {
 typedef struct fdl_batch_plan fdl_batch_plan;
 
 /* descs_host: B descriptors in HOST memory (their pointers are device
- * pointers).  Light fields are grouped by channel count, disparity class and
- * row-slot class (n <= 16 or n <= 32).  mode 0 = flat: one block per 16-bin
- * tile, one launch per group; mode 1 = persistent: a grid of (blocks per CU x
- * CUs) blocks pulls tiles from an atomic queue, one launch per group; mode 2
- * = flat single: every light field through the n <= 32 solver, so one launch
+ * pointers).  Light fields are grouped by channel count and disparity class.
+ * mode 0 = flat: one block per 16-bin tile, one launch per solved-row class
+ * (the smallest of 8, 16, 20, 24, 28, 30, 32 rows that holds n); mode 1 =
+ * persistent: a grid of (blocks per CU x CUs) blocks pulls tiles from an
+ * atomic queue, one launch per row-slot class (n <= 16 or n <= 32); mode 2 =
+ * flat single: every light field through the n <= 32 solver, so one launch
  * covers all light fields of a channel/disparity class; mode 3 = persistent
  * single: the atomic queue of mode 1 over all light fields of a
  * channel/disparity class through the n <= 32 solver (one launch per class).
- * Tiles are ordered largest light field first.  The disparities of each light
- * field are read once (blocking) and classified as fdl_construct does.
- * Argument errors as fdl_construct. */
+ * Launches are ordered largest group first, tiles largest light field first
+ * within a launch.  The disparities of each light field are read once
+ * (blocking) and classified as fdl_construct does.  Argument errors as
+ * fdl_construct. */
 int fdl_batch_plan_create(const fdl_lf_desc* descs_host, int B, int mode, fdl_batch_plan** plan_out);
 /* Enqueue the plan's launch(es) on `stream`; allocates nothing and issues no
  * memset (each persistent launch's last block resets its queue), so it may be

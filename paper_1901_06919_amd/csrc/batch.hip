@@ -5,10 +5,10 @@
 // tile table (light field, first bin), ordered largest-work-first; the
 // 16 teams of a block solve the tile's 16 bins with the same team solver as
 // the plain kernels.  Launch modes: flat (one block per tile, one launch per
-// channel/disparity/row-slot class), flat single (every light field through
+// channel/disparity/solved-row class), flat single (every light field through
 // the n <= 32 solver: one launch per channel/disparity class), persistent
 // (a machine-sized grid pulling tiles from an atomic queue, one launch per
-// class; the last block resets the queue so replays need no memset) and
+// row-slot class; the last block resets the queue so replays need no memset) and
 // persistent single (the queue over every light field of a channel/disparity
 // class through the n <= 32 solver: one launch when all share the class).  The
 // autotuner times the candidates on the plan's own data and keeps the
@@ -20,88 +20,11 @@
 #include <vector>
 
 #include "../../include/fdl.h"
-#include "construct_team.h"
+#include "batch_kernels.h"
 
-namespace fdl {
-
-struct Tile {   // 16 bins of one light field (one bin per team)
-  int lf;
-  int f0;
-};
-
-// Opaque copy of the lane index: keeps the lane-dependent predicates of the
-// unrolled solver inside loops instead of letting them be hoisted (and held
-// in registers) across iterations.  Emits no instruction.
-__device__ __forceinline__ int opaque_lane(int lane) {
-  asm volatile("" : "+v"(lane));
-  return lane;
-}
-
-// Flat modes: one block per tile.  R is the row-slot class of the launch
-// (R = 2 also solves n <= 16, so a single launch can cover every light field).
-template <int CT, bool TOEP, int R>
-__global__ __launch_bounds__(256, TOEP && R > 1 ? 2 : 1) void k_batched_flat(const ConstructParams* __restrict__ lfs,
-                                                      const Tile* __restrict__ tiles) {
-  __shared__ TeamLds<R> s_team[16];
-  __shared__ double2 s_tab[kPhaseTab];
-  fill_phase_table(s_tab);
-  __syncthreads();
-  const int lane = threadIdx.x & 15;
-  const int team = threadIdx.x >> 4;
-  // tiles are sorted by light-field cost, so they are NOT remapped to
-  // contiguous per-XCD ranges: the dispatcher's round-robin spreads every
-  // light field over all XCDs and keeps their loads balanced
-  const int t = blockIdx.x;
-  const int lf = __builtin_amdgcn_readfirstlane(tiles[t].lf);
-  const int f0 = __builtin_amdgcn_readfirstlane(tiles[t].f0);
-  const ConstructParams* P = lfs + lf;
-  const int f = f0 + team;
-  if (f >= P->F) return;
-  team_solve<R, CT, TOEP>(*P, s_team[team], s_tab, f, lane);
-}
-
-// Persistent mode: a grid sized to the machine pulls `chunk` tiles at a time
-// from an atomic queue; one launch per row-slot class R.  The last block out
-// resets the queue, so replays need no memset.
-template <int CT, bool TOEP, int R>
-__global__ __launch_bounds__(256, TOEP && R > 1 ? 2 : 1) void k_batched_persistent(const ConstructParams* __restrict__ lfs,
-                                                            const Tile* __restrict__ tiles, int ntiles, int chunk,
-                                                            int* counters) {
-  __shared__ TeamLds<R> s_team[16];
-  __shared__ double2 s_tab[kPhaseTab];
-  __shared__ int s_tile;
-  fill_phase_table(s_tab);
-  const int lane = threadIdx.x & 15;
-  const int team = threadIdx.x >> 4;
-  for (;;) {
-    if (threadIdx.x == 0) s_tile = atomicAdd(&counters[0], chunk);
-    __syncthreads();
-    const int t0 = __builtin_amdgcn_readfirstlane(s_tile);
-    __syncthreads();
-    if (t0 >= ntiles) break;
-    const int t1 = min(t0 + chunk, ntiles);
-    for (int t = t0; t < t1; ++t) {
-      const int lf = __builtin_amdgcn_readfirstlane(tiles[t].lf);
-      const int f0 = __builtin_amdgcn_readfirstlane(tiles[t].f0);
-      const ConstructParams* P = lfs + lf;
-      const int f = f0 + team;
-      if (f < P->F) team_solve<R, CT, TOEP>(*P, s_team[team], s_tab, f, opaque_lane(lane));
-    }
-  }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int done = atomicAdd(&counters[1], 1);
-    if (done == (int)gridDim.x - 1) {
-      atomicExch(&counters[0], 0);
-      atomicExch(&counters[1], 0);
-    }
-  }
-}
-
-}  // namespace fdl
 
 struct BatchLaunch {            // one launch over a group of tiles
-  int ct, toep, r;              // row-slot class of the launch (1: n <= 16, 2: n <= 32)
+  int ct, toep, r, nf;          // row slots (1: n <= 16, 2: n <= 32) and solved rows of the launch
   int tile_off, ntiles;         // slice of the device tile table
   int grid;
   int* counters;                // 2 ints in device memory (persistent mode)
@@ -109,7 +32,7 @@ struct BatchLaunch {            // one launch over a group of tiles
 
 struct fdl_batch_plan {
   int B = 0;
-  int mode = 0;                 // 0 flat per row-slot class, 1 persistent, 2 flat single, 3 persistent single
+  int mode = 0;                 // 0 flat per solved-row class, 1 persistent, 2 flat single, 3 persistent single
   int chunk = 1;                // tiles claimed per queue access (persistent)
   int grid_per_cu = 2;          // resident blocks per CU (persistent)
   int64_t total_bins = 0;
@@ -138,31 +61,50 @@ int cu_count() {
 bool persistent_mode(int mode) { return mode == 1 || mode == 3; }
 
 double lf_cost(const fdl::ConstructParams& P) {
-  // per-bin work of the team solver grows with m (views), C and the row slots
-  const double R = P.n <= 16 ? 1.0 : 2.0;
-  return (double)P.F * (double)P.m * (2.0 + P.C) * R;
+  // rough lane instructions per bin: the view loop (phases, right-hand sides
+  // and Gram sums of R row slots) plus the factorisation and substitutions of
+  // the solved rows
+  const int nf = fdl::solve_rows(P.n);
+  const double R = nf > 16 ? 2.0 : 1.0;
+  return (double)P.F * ((double)P.m * (30.0 + (4.0 * P.C + 6.0) * R) + 2.5 * nf * nf + 8.0 * nf * P.C);
 }
 
 // (Re)build the tile table and launch groups for the plan's current settings.
 int build_tiles(fdl_batch_plan* p) {
-  struct Group { int ct, toep, r; std::vector<int> lfs; };
+  struct Group { int ct, toep, r, nf; std::vector<int> lfs; double cost = 0.0; };
   std::vector<Group> groups;
   for (int i = 0; i < p->B; ++i) {
     const auto& P = p->host_params[i];
     const int ct = P.C == 1 ? 1 : (P.C <= 3 ? 3 : 4);
-    const int r = (p->mode == 2 || p->mode == 3) ? 2 : (P.n <= 16 ? 1 : 2);
+    // flat mode: one launch per solved-row class; single modes: every light
+    // field through the 32-row solver; persistent: the 16- and 32-row solvers
+    int r, nf;
+    if (p->mode == 2 || p->mode == 3) {
+      r = 2; nf = 32;
+    } else if (p->mode == 1) {
+      r = P.n <= 16 ? 1 : 2; nf = 16 * r;
+    } else {
+      nf = fdl::solve_rows(P.n); r = nf > 16 ? 2 : 1;
+    }
     bool found = false;
     for (auto& g : groups)
-      if (g.ct == ct && g.toep == P.toeplitz && g.r == r) { g.lfs.push_back(i); found = true; break; }
-    if (!found) groups.push_back(Group{ct, P.toeplitz, r, {i}});
+      if (g.ct == ct && g.toep == P.toeplitz && g.nf == nf) { g.lfs.push_back(i); found = true; break; }
+    if (!found) groups.push_back(Group{ct, P.toeplitz, r, nf, {i}, 0.0});
   }
+  // largest groups first
+  for (auto& g : groups) {
+    double c = 0.0;
+    for (int lf : g.lfs) c += lf_cost(p->host_params[lf]);
+    g.cost = c;
+  }
+  std::stable_sort(groups.begin(), groups.end(), [](const Group& a, const Group& b) { return a.cost > b.cost; });
   std::vector<fdl::Tile> tiles;
   p->launches.clear();
   int gi = 0;
   for (auto& g : groups) {
     std::sort(g.lfs.begin(), g.lfs.end(), [&](int a, int b) { return lf_cost(p->host_params[a]) > lf_cost(p->host_params[b]); });
     BatchLaunch L;
-    L.ct = g.ct; L.toep = g.toep; L.r = g.r;
+    L.ct = g.ct; L.toep = g.toep; L.r = g.r; L.nf = g.nf;
     L.tile_off = (int)tiles.size();
     for (int lf : g.lfs)
       for (int f0 = 0; f0 < p->host_params[lf].F; f0 += 16) tiles.push_back(fdl::Tile{lf, f0});
@@ -185,27 +127,21 @@ int build_tiles(fdl_batch_plan* p) {
   return FDL_OK;
 }
 
-template <int CT, bool TOEP>
-hipError_t go(const fdl_batch_plan* p, const BatchLaunch& L, hipStream_t s) {
-  const fdl::Tile* t = p->d_tiles + L.tile_off;
-  if (!persistent_mode(p->mode)) {
-    if (L.r == 1)
-      hipLaunchKernelGGL((fdl::k_batched_flat<CT, TOEP, 1>), dim3(L.grid), dim3(256), 0, s, p->d_params, t);
-    else
-      hipLaunchKernelGGL((fdl::k_batched_flat<CT, TOEP, 2>), dim3(L.grid), dim3(256), 0, s, p->d_params, t);
-  } else if (L.r == 1)
-    hipLaunchKernelGGL((fdl::k_batched_persistent<CT, TOEP, 1>), dim3(L.grid), dim3(256), 0, s, p->d_params, t,
-                       L.ntiles, p->chunk, L.counters);
-  else
-    hipLaunchKernelGGL((fdl::k_batched_persistent<CT, TOEP, 2>), dim3(L.grid), dim3(256), 0, s, p->d_params, t,
-                       L.ntiles, p->chunk, L.counters);
-  return hipGetLastError();
-}
-
 hipError_t launch_group(const fdl_batch_plan* p, const BatchLaunch& L, hipStream_t s) {
-  if (L.ct == 1) return L.toep ? go<1, true>(p, L, s) : go<1, false>(p, L, s);
-  if (L.ct == 3) return L.toep ? go<3, true>(p, L, s) : go<3, false>(p, L, s);
-  return L.toep ? go<4, true>(p, L, s) : go<4, false>(p, L, s);
+  fdl::BatchArgs a;
+  a.params = p->d_params;
+  a.tiles = p->d_tiles + L.tile_off;
+  a.ntiles = L.ntiles;
+  a.grid = L.grid;
+  a.chunk = p->chunk;
+  a.counters = L.counters;
+  a.toep = L.toep;
+  a.r = L.r;
+  a.nf = L.nf;
+  a.persistent = persistent_mode(p->mode);
+  if (L.ct == 1) return fdl::batch_launch_c1(a, s);
+  if (L.ct == 3) return fdl::batch_launch_c3(a, s);
+  return fdl::batch_launch_c4(a, s);
 }
 
 }  // namespace

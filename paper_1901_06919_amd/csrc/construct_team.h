@@ -585,6 +585,10 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
       const double ei = kTwoPi * T.m.e[i];
       static_for<0, 16 * (r + 1)>([&](auto KK) {
         constexpr int k = decltype(KK)::value;
+        if constexpr (k >= NF) {   // column outside the solved rows
+          S.template at<r>(k) = cd{0.0, 0.0};
+          return;
+        }
         const int t = (i - k) & 31;
         const double2 q0 = T.m.r0[t];
         const double2 q1 = T.m.r1[t];
@@ -613,6 +617,7 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
       const double ci = lw * dk[r] * dk[r];
       static_for<0, 16 * (r + 1)>([&](auto KK) {
         constexpr int k = decltype(KK)::value;
+        if constexpr (k >= NF) return;
         const double dkk = P.d[k];
         const double dd = dk[r] - dkk;
         const double g = ci * dkk * dkk * (double)(sinc_pi(rx * dd) * sinc_pi(ry * dd));
@@ -732,8 +737,8 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   if constexpr (R == 1) {
     // row layout: x_i = (y_i - sum_{k>i} conj(L_ki) x_k) / L_ii, the sum over
     // the team's lanes by a DPP reduction
-    static_for<0, NMAX>([&](auto II) {
-      constexpr int i = NMAX - 1 - decltype(II)::value;
+    static_for<0, NF>([&](auto II) {
+      constexpr int i = NF - 1 - decltype(II)::value;
 #pragma unroll
       for (int c = 0; c < CT; ++c) {
         cd s = cd{0.0, 0.0};

@@ -37,8 +37,22 @@ struct RenderParams {
   int n, C, H, W, Wh, F, V;
 };
 
-hipError_t launch_construct_r1(const ConstructParams& P, hipStream_t s);   // n <= 16
-hipError_t launch_construct_r2(const ConstructParams& P, hipStream_t s);   // n <= 32
+// Rows factorised by the team solver for n layers: the smallest class that
+// holds n (the rows between n and the class are an identity block).  One
+// kernel instantiation per class, so that small systems skip the padded work.
+constexpr int kSolveRowClasses[] = {8, 16, 20, 24, 28, 30, 32};
+inline int solve_rows(int n) {
+  for (int c : kSolveRowClasses)
+    if (n <= c) return c;
+  return 32;
+}
+// plain construction (one 16-lane team per half-spectrum bin), by channel class
+hipError_t launch_construct_c1(const ConstructParams& P, hipStream_t s);   // C == 1
+hipError_t launch_construct_c3(const ConstructParams& P, hipStream_t s);   // C <= 3
+hipError_t launch_construct_c4(const ConstructParams& P, hipStream_t s);   // C <= 4
+inline hipError_t launch_construct(const ConstructParams& P, hipStream_t s) {
+  return P.C == 1 ? launch_construct_c1(P, s) : (P.C <= 3 ? launch_construct_c3(P, s) : launch_construct_c4(P, s));
+}
 hipError_t launch_construct_views(const ConstructParams& P, hipStream_t s);   // inputs with apertures
 hipError_t launch_construct_relaxed(const ConstructParams& P, hipStream_t s);   // free shifts per view and layer
 hipError_t launch_construct_region(const ConstructParams& P, hipStream_t s);    // finite-region view regulariser

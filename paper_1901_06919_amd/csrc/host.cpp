@@ -129,7 +129,7 @@ int fdl_construct_bins(const fdl_c64* view_spec_dev, const fdl_f2* u_dev, const 
   fdl_host::classify(d_host, n, P);
   trace("construct m n C F", m, n, C, (int)F);
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  return map_hip(n <= 16 ? fdl::launch_construct_r1(P, s) : fdl::launch_construct_r2(P, s));
+  return map_hip(fdl::launch_construct(P, s));
 }
 
 int fdl_construct_views(const fdl_c64* view_spec_dev, const fdl_view* views_dev, const float* d_host, int m, int n,

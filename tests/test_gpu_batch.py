@@ -41,7 +41,7 @@ def _plain(items):
             for it in items]
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
 def test_batched_matches_plain_calls(mode):
     items = _items(12, sizes=(128, 256, 384), seed=mode)
     ref = _plain(items)

@@ -63,6 +63,29 @@ def test_construct_matches_oracle(m, n, C, H, W, uniform, reg):
     assert err < TOL
 
 
+# one case per kernel instantiation: every solved-row class (8, 16, 20, 24,
+# 28, 30, 32 rows), channel class (1, 2-3, 4) and disparity class
+SOLVER_CLASSES = [(n, C, uniform) for n in (5, 12, 19, 23, 27, 29, 31, 32) for C in (1, 2, 4)
+                  for uniform in (True, False)]
+
+
+@pytest.mark.parametrize("n,C,uniform", SOLVER_CLASSES)
+def test_construct_every_solver_class(n, C, uniform):
+    m, H, W = 6, 6, 8
+    print(f"construct class case n={n} C={C} uniform={uniform}", flush=True)
+    u, d, spec = _rand_case(7000 + 3 * n + C, m, n, C, H, W, uniform)
+    reg = O.REG_VIEW2 if uniform else O.REG_L2
+    lam, eps = 1e-2, 1e-3
+    ref = O.construct(spec.astype(np.complex128), u.astype(np.float64), d.astype(np.float64), H, W, lam, eps, reg)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    got = fdl().construct(dev(spec), dev(u), dev(d), H, W, lam, eps, reg, status=st)
+    torch.cuda.synchronize()
+    err = O.rel_l2(got.cpu().numpy(), ref)
+    print(f"  rel_l2 = {err:.3e} status {st.item()}")
+    assert st.item() == 0
+    assert err < TOL
+
+
 def test_construct_5x5_128_full_size():
     """The 5x5-view light field at full size (128^2, 8 layers), views from the oracle's forward model."""
     spec_in = synth.lf_5x5_128()
