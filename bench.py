@@ -53,7 +53,7 @@ def construct_flops_per_bin(m: int, n: int, C: int) -> int:
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for name in ("construct_team.h", "construct_r2.hip", "fdl_device.h"):
+    for name in ("construct_team.h", "construct_plain.h", "construct_c3.hip", "fdl_device.h"):
         with open(os.path.join(ROOT, "paper_1901_06919_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -511,8 +511,13 @@ def main():
     ach = achievable(fdl, dev)
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_TFLOPS, "traffic": cnt.get("hbm_bytes_per_launch"),
-            "kernel": "k_construct<2,3,true>", "flops_per_launch": flops,
+            "kernel": "k_construct<3,true,30>", "flops_per_launch": flops,
             "achievable_peak": ach["fp64_fma_TFLOPs"], "frac_of_achievable": achieved / ach["fp64_fma_TFLOPs"]}
+    if cnt:
+        # traffic and instruction counts are not observed in this run: they
+        # come from the committed counter record of the same kernel source
+        roof["counters_source"] = ("committed rocprofv3 record profiles/construct_9x9_512rgb_traffic.json "
+                                   f"(kernel source {cnt.get('kernel_source_hash')}, {cnt.get('source')})")
     if cnt.get("valu_insts_per_launch"):
         # time the counted VALU instructions need at one wave instruction per
         # 4 cycles on each of the 1024 SIMDs at 2.4 GHz, over the measured time
