@@ -2,7 +2,9 @@
 leave-one-out adjoint) and the normalised gradient step, against the FP64
 oracle; the LOO adjoint is also checked against central finite differences of
 the FP64 loss on every bin of the 7x7, 256^2, 16-layer workload."""
+import json
 import math
+import os
 
 import numpy as np
 import pytest
@@ -129,6 +131,19 @@ def test_loo_adjoint_vs_finite_differences_7x7_256_all_bins():
         scale = max(np.abs(gu2.cpu().numpy()).max(), np.abs(gd2.cpu().numpy()).max())
         print(f"  {kind}[{i},{c}] adjoint {g:+.8e} fd {fd:+.8e}")
         assert abs(g - fd) <= 1e-5 * scale
+    # directional derivatives along random unit directions in all (u, d)
+    # coordinates at once: every one of the 2m + n gradient entries takes part
+    gall = np.concatenate([gu2.cpu().numpy().ravel(), gd2.cpu().numpy()])
+    rng = np.random.default_rng(77)
+    for k in range(3):
+        v = rng.standard_normal(gall.shape[0])
+        v /= np.linalg.norm(v)
+        vu, vd = v[:u.size].reshape(u.shape), v[u.size:]
+        fd = (_press_loss_all_bins(b64, u + h * vu, d + h * vd, H, W, spec.lam, spec.eps)
+              - _press_loss_all_bins(b64, u - h * vu, d - h * vd, H, W, spec.lam, spec.eps)) / (2 * h)
+        g = float(gall @ v)
+        print(f"  direction {k}: adjoint {g:+.8e} fd {fd:+.8e}")
+        assert abs(g - fd) <= 1e-5 * np.linalg.norm(gall)
 
 
 def test_calib_is_deterministic():
@@ -156,30 +171,54 @@ def test_gd_step_matches_oracle():
     np.testing.assert_allclose(td.cpu().numpy(), dr, rtol=0, atol=2e-7)
 
 
-def test_calibration_trajectory_first_steps():
-    """20 LOO gradient steps (alpha 0.2, fresh 512-bin subset per step, passed
-    to both sides) on the 7x7 / 256^2 / 16-layer workload: parameters after
-    every step within 1e-4 (relative L2) of the oracle's trajectory."""
+def _stored_trajectory():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "calib_trajectory_7x7_256_q4096.json")) as fh:
+        return json.load(fh)
+
+
+def test_calib_loo_4096_bins_matches_stored_oracle():
+    """LOO loss and gradient on 4096 bins of the 7x7 / 256^2 / 16-layer
+    workload (several bins per block) at the start point, against the FP64
+    oracle's values stored with its trajectory (first step)."""
+    ref = _stored_trajectory()
+    spec, u0, d0, b = _calib_inputs()
+    H, W = spec.H, spec.W
+    S = synth.frequency_subset(H * (W // 2 + 1), ref["Q"], np.random.default_rng(ref["seed"]))
+    assert int(np.sum(S.astype(np.int64))) == ref["subset_sums"][0], "subset generator changed"
+    l2, gu2, gd2 = fdl().calib_grad(dev(b), dev(u0), dev(d0), H, W, spec.lam, spec.eps, spec.reg, O.LOSS_LOO, dev(S))
+    torch.cuda.synchronize()
+    el = abs(l2.item() - ref["loss"][0]) / abs(ref["loss"][0])
+    eu = rel(gu2.cpu().numpy().ravel(), ref["grad_u"][0])
+    ed = rel(gd2.cpu().numpy(), ref["grad_d"][0])
+    print(f"LOO Q=4096: loss rel {el:.2e}, grad u {eu:.2e}, grad d {ed:.2e}")
+    assert el < 1e-6 and eu < 1e-5 and ed < 1e-5
+
+
+def test_calibration_trajectory_20_steps_4096_bins():
+    """20 LOO gradient steps (alpha 0.2, a fresh 4096-bin subset per step) on
+    the 7x7 / 256^2 / 16-layer workload: the parameters after every step within
+    1e-4 (relative L2) of the FP64 oracle's trajectory, and the loss at every
+    step within 1e-5 of the oracle's.  The oracle's trajectory is stored by
+    tests/golden/make_calib_trajectory.py (oracle only, same seeds), since it
+    takes minutes on the host."""
+    ref = _stored_trajectory()
     spec, u0, d0, b = _calib_inputs()
     H, W = spec.H, spec.W
     F = H * (W // 2 + 1)
-    rng = np.random.default_rng(505)
-    u_o, d_o = u0.astype(np.float64), d0.astype(np.float64)
+    rng = np.random.default_rng(ref["seed"])
     tu, td = dev(u0), dev(d0)
     tb = dev(b)
-    b64 = b.astype(np.complex128)
-    for step in range(20):
-        S = synth.frequency_subset(F, 512, rng)
-        _, gu, gd = O.calib_loss_grad(b64, u_o, d_o, H, W, spec.lam, spec.eps, spec.reg, O.LOSS_LOO, S)
-        u_o, d_o = O.gd_step(u_o, d_o, gu, gd, 0.2, 1e-6)
-        u_o, d_o = u_o.astype(np.float32).astype(np.float64), d_o.astype(np.float32).astype(np.float64)
-        _, tgu, tgd = fdl().calib_grad(tb, tu, td, H, W, spec.lam, spec.eps, spec.reg, O.LOSS_LOO, dev(S))
-        fdl().gd_step(tu, td, tgu, tgd, 0.2, 1e-6)
+    for step in range(ref["steps"]):
+        S = synth.frequency_subset(F, ref["Q"], rng)
+        assert int(np.sum(S.astype(np.int64))) == ref["subset_sums"][step], "subset generator changed"
+        tl, tgu, tgd = fdl().calib_grad(tb, tu, td, H, W, spec.lam, spec.eps, spec.reg, O.LOSS_LOO, dev(S))
+        fdl().gd_step(tu, td, tgu, tgd, ref["alpha"], ref["eps_g"])
         torch.cuda.synchronize()
-        eu = rel(tu.cpu().numpy(), u_o)
-        ed = rel(td.cpu().numpy(), d_o)
-        print(f"  step {step}: rel u {eu:.2e} d {ed:.2e}")
-        assert eu < 1e-4 and ed < 1e-4
+        eu = rel(tu.cpu().numpy().ravel(), ref["u"][step])
+        ed = rel(td.cpu().numpy(), ref["d"][step])
+        el = abs(tl.item() - ref["loss"][step]) / abs(ref["loss"][step])
+        print(f"  step {step}: loss rel {el:.2e}, rel u {eu:.2e} d {ed:.2e}")
+        assert eu < 1e-4 and ed < 1e-4 and el < 1e-5
 
 
 @pytest.mark.parametrize("relaxed", [False, True])
