@@ -503,31 +503,25 @@ __global__ __launch_bounds__(256) void k_fft_cols(float2* __restrict__ data, int
   }
 }
 
-// Largest dynamic LDS a block may request on this device (opted in once per
-// kernel when above the 64 KiB default).
+// Largest dynamic LDS a block may request on the current device (queried on
+// every call: no process-wide cache, so each device answers for itself).
 static size_t max_block_lds() {
-  static size_t cached = 0;
-  if (!cached) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
-      cached = (size_t)v;
-    else
-      cached = 65536;
-  }
-  return cached;
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+    return (size_t)v;
+  return 65536;
 }
 
 size_t fft_lds_limit() { return max_block_lds(); }
 
+// Dynamic LDS above the 64 KiB default is opted in on every such launch (the
+// attribute is per device and the call is cheap; no process-wide state).
 template <bool INV>
 static void opt_in_lds(size_t bytes) {
-  static size_t done = 65536;
-  if (bytes > done) {
-    hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_cols<INV>), hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)bytes);
-    done = bytes;
-  }
+  if (bytes > 65536)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_fft_cols<INV>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
 static int pick_threads(int N) {
