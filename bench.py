@@ -51,11 +51,38 @@ def construct_flops_per_bin(m: int, n: int, C: int) -> int:
     return 8 * m * (n - 1) + 8 * m * n * C + (4 * n ** 3) // 3 + 8 * n * n * C
 
 
+def _code_only(text: str) -> str:
+    """C++ source with comments removed and whitespace collapsed, so that the
+    hash below changes with the code and not with its comments."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c == '"' or c == "'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
+    """Hash of the construction kernel's code (comments and layout ignored);
+    the committed counter record is used only while it matches."""
     h = hashlib.sha256()
     for name in ("construct_team.h", "construct_plain.h", "construct_c3.hip", "fdl_device.h"):
-        with open(os.path.join(ROOT, "paper_1901_06919_amd", "csrc", name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, "paper_1901_06919_amd", "csrc", name)) as f:
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -178,10 +178,9 @@ struct TeamRhs {
 // LDS banks); only the R = 2 solver uses it, after the moments are dead.
 constexpr int kTrStride = 17;
 
-// One team's LDS.  The 16-byte pad after the union makes the per-team
-// stride an odd multiple of 16 bytes modulo the 256-byte bank period, so that
-// the four teams of a wave, reading the same offset of their own areas (the
-// view records), hit different banks.
+// One team's LDS: the view records and moments of the Gram phase, the
+// right-hand sides parked during the factorisation and the transposition tile
+// of the backward pass are never live together, so they share one area.
 template <int R>
 union TeamLds {
   TeamMoments m;
