@@ -246,6 +246,66 @@ __device__ __forceinline__ void team_transpose(TeamRows<R>& S, double2* tr, int 
   team_sync();
 }
 
+// Views on a complete lattice in raster order: u_j = o + a g1 + b g2 for
+// j = a B + b, a < A, b < B (a plenoptic camera's sub-aperture views).  Then
+// p_j = <u_j, w> = <o, w> + a <g1, w> + b <g2, w>, and each phase of Sec. V-A
+// factors as exp(2 pi i e p_j) = exp(2 pi i e <o, w>) U^a V^b with
+// U = exp(2 pi i e <g1, w>), V = exp(2 pi i e <g2, w>): the Toeplitz view loop
+// steps from one view's phase to the next with one complex product.
+struct ViewLattice {
+  double ox, oy, g1x, g1y, g2x, g2y;
+  int B;
+  bool ok;   // the positions satisfy the identity exactly, with B <= 16
+};
+
+// Test of the positions by one team (every lane gets the same result; the
+// other teams of the wave, if active, test the same positions).  B is the
+// first index that leaves the progression u_0 + j (u_1 - u_0); the identity is
+// then checked for every view in FP64, where the differences and small
+// multiples of float positions are exact, so any mismatch selects the table
+// path.  Positions off a lattice usually fail at j = 2 or on m mod B.
+__device__ __forceinline__ ViewLattice find_view_lattice(const float2* __restrict__ u, int m, int lane) {
+  ViewLattice L;
+  const float2 u0 = u[0];
+  const float2 u1 = u[m > 1 ? 1 : 0];
+  L.ox = u0.x;
+  L.oy = u0.y;
+  L.g2x = (double)u1.x - L.ox;
+  L.g2y = (double)u1.y - L.oy;
+  // lane l tests j = l + 2 (2 <= j <= 16)
+  bool off = false;
+  const int jb = lane + 2;
+  if (jb < m && jb <= 16) {
+    const float2 v = u[jb];
+    off = (double)v.x != fma((double)jb, L.g2x, L.ox) || (double)v.y != fma((double)jb, L.g2y, L.oy);
+  }
+  const unsigned long long brk = __ballot(off);
+  int B = m;
+  if (brk != 0)
+    B = (__ffsll((long long)brk) - 1) % 16 + 2;   // first break in any active team (all test the same j)
+  else if (m > 17)
+    B = 17;                                       // no break up to j = 16: a row longer than 16 views
+  L.B = B;
+  L.ok = false;
+  if (B > 16 || m % B != 0) return L;
+  const float2 uB = u[B < m ? B : 0];
+  L.g1x = (double)uB.x - L.ox;
+  L.g1y = (double)uB.y - L.oy;
+  // a = floor(j / B) from (j + 1/2) / B, which stays at least 1/32 away from
+  // an integer (B <= 16) while its float error is below 1e-3 (j < 2^14)
+  const float rb = 1.0f / (float)B;
+  bool bad = false;
+  for (int j = lane; j < m; j += 16) {
+    const int a = (int)(((float)j + 0.5f) * rb);
+    const int b = j - a * B;
+    const float2 v = u[j];
+    bad = bad || (double)v.x != fma((double)a, L.g1x, fma((double)b, L.g2x, L.ox)) ||
+          (double)v.y != fma((double)a, L.g1y, fma((double)b, L.g2y, L.oy));
+  }
+  L.ok = __ballot(bad) == 0;
+  return L;
+}
+
 // APER: the inputs carry their own apertures (Eq. AMatGeneral):
 // A_jk = exp(2 pi i d_k p_j) psi_hat_j((s_j - d_k) w), general Gram path only.
 // SHIFTS: the relaxed model (Sec. VIII-B), a free shift pair per view and
@@ -402,26 +462,30 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   };
   if constexpr (TOEP) {
     // Toeplitz path.  Everything the lanes share about view j is formed once,
-    // by one lane, for a batch of 16 views and staged in LDS:
+    // by one lane, for a batch of up to 16 views and staged in LDS:
     //   beta_jc = conj(A_j0) b_jc, Z_j = exp(2 pi i (d_16 - d_0) p_j), p_j, p_j^2.
-    // Lane l then needs only W_jt = conj(A_j0) A_jt for its rows t = l, l + 16:
+    // Lane l then needs only W_jt = conj(A_j0) A_jt for its rows t = l, l + 16
+    // and accumulates c_t += conj(W_jt) beta_jc (= conj(A_jt) b_jc) and the
+    // moments R_q,t = sum_j p_j^q W_jt.  W_jt is formed in one of two ways.
+    //
+    // Table path (any positions):
     //   W_jl = exp(2 pi i (d_l - d_0) p_j) from the table, and
     //   W_j,l+16 = W_jl Z_j exp(i phi), phi = 2 pi eta_l p_j,
     //   eta_l = (d_{l+16} - d_l) - (d_16 - d_0) (float rounding; |eta_l| <=
     //   eta_max, so |phi| <= 3e-4 when the status check passes, and the series
-    //   1 - phi^2/2 + i phi is exact to 5e-12),
-    // and accumulates c_t += conj(W_jt) beta_jc (= conj(A_jt) b_jc) and the
-    // moments R_q,t += p_j^q W_jt.
+    //   1 - phi^2/2 + i phi is exact to 5e-12); the moments are summed per view.
+    //
+    // Lattice path (ViewLattice): the batches are the lattice rows, and
+    //   W_jt = E_t U_t^a V_t^b is stepped along a row by V_t and from row to
+    //   row by U_t.  The row start is recomputed from the table every 8 rows,
+    //   so at most 7 + 15 rounded products separate a phase from a table value
+    //   (relative error below 1e-14).  The moments follow in closed form from
+    //   sums over the rows and along a row (below), so a view costs only its
+    //   right-hand-side products and one step.
     double2* rec = T.m.views;
     constexpr int RS = CT + 2;   // record: beta[CT], Z, (p, p^2)
     const double dt0 = kPhaseTab * d0;
-    const double dtl = kPhaseTab * T.m.e[lane];
-    double c1 = 0.0, h1 = 0.0, dtz = 0.0;
-    if constexpr (R > 1) {
-      c1 = kTwoPi * ((T.m.e[lane + 16] - T.m.e[lane]) - T.m.e[16]);
-      h1 = -0.5 * c1 * c1;
-      dtz = kPhaseTab * T.m.e[16];
-    }
+    const ViewLattice lat = find_view_lattice(P.u, m, lane);
     // raw inputs of the next batch (lane l: view j0 + l), loaded one batch ahead
     float2 nu, nb[CT];
     auto fetch = [&](int j0) {
@@ -430,58 +494,151 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
 #pragma unroll
       for (int c = 0; c < CT; ++c) nb[c] = P.view_spec[((size_t)jc * C + (c < C ? c : C - 1)) * F + f];
     };
-    fetch(0);
-    for (int j0 = 0; j0 < m; j0 += kViewBatch) {
+    // stages the records of views j0 .. j0 + nbv - 1 (lane l: view j0 + l)
+    // and fetches the next batch; the lattice path needs neither Z nor p
+    auto produce = [&](int j0, int nbv, double dtz, bool full) {
       const float2 uu = nu;
       float2 bb[CT];
 #pragma unroll
       for (int c = 0; c < CT; ++c) bb[c] = nb[c];
-      if (j0 + kViewBatch < m) fetch(j0 + kViewBatch);
-      {
-        const bool valid = j0 + lane < m;
-        const double p = fma((double)uu.x, wx, (double)uu.y * wy);
-        const cd a0 = expi_tab(tab, dt0, p);
-        cd z = cd{1.0, 0.0};
-        if constexpr (R > 1) z = expi_tab(tab, dtz, p);
-        pmax = fmax(pmax, valid ? fabs(p) : 0.0);
-        team_sync();   // the previous batch's records have been read
+      if (j0 + nbv < m) fetch(j0 + nbv);
+      const bool valid = lane < nbv && j0 + lane < m;
+      const double p = fma((double)uu.x, wx, (double)uu.y * wy);
+      const cd a0 = expi_tab(tab, dt0, p);
+      cd z = cd{1.0, 0.0};
+      if constexpr (R > 1)
+        if (full) z = expi_tab(tab, dtz, p);
+      pmax = fmax(pmax, valid ? fabs(p) : 0.0);
+      team_sync();   // the previous batch's records have been read
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          const cd be = valid ? cmulc(a0, cd{(double)bb[c].x, (double)bb[c].y}) : cd{0.0, 0.0};
-          rec[lane * RS + c] = make_double2(be.re, be.im);
-        }
+      for (int c = 0; c < CT; ++c) {
+        const cd be = valid ? cmulc(a0, cd{(double)bb[c].x, (double)bb[c].y}) : cd{0.0, 0.0};
+        rec[lane * RS + c] = make_double2(be.re, be.im);
+      }
+      if (full) {
         rec[lane * RS + CT] = make_double2(z.re, z.im);
         rec[lane * RS + CT + 1] = make_double2(p, p * p);
-        team_sync();
       }
-      const int nv = min(kViewBatch, m - j0);
-#pragma unroll 2
-      for (int v = 0; v < nv; ++v) {
-        const double2* q = rec + v * RS;
-        const double2 pp = q[CT + 1];
-        const double p = pp.x, p2 = pp.y;
+      team_sync();
+    };
+    if (lat.ok) {
+      const int B = lat.B;
+      const double po = fma(lat.ox, wx, lat.oy * wy);
+      const double pg1 = fma(lat.g1x, wx, lat.g1y * wy);
+      const double pg2 = fma(lat.g2x, wx, lat.g2y * wy);
+      double dte[R];
+      cd Srow[R], Ust[R], Vst[R];
+      // sums over the lattice rows of a^k E U^a, k = 0, 1, 2
+      cd T0[R], T1[R], T2[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        dte[r] = kPhaseTab * T.m.e[lane + 16 * r];
+        Srow[r] = expi_tab(tab, dte[r], po);
+        Ust[r] = expi_tab(tab, dte[r], pg1);
+        Vst[r] = expi_tab(tab, dte[r], pg2);
+        T0[r] = T1[r] = T2[r] = cd{0.0, 0.0};
+      }
+      fetch(0);
+      int arow = 0;
+      for (int j0 = 0; j0 < m; j0 += B, ++arow) {
+        produce(j0, B, 0.0, false);
+        const double fa = (double)arow, fa2 = fa * fa;
         cd W[R];
-        W[0] = expi_tab(tab, dtl, p);
-        if constexpr (R > 1) {
-          const double2 zz = q[CT];
-          const cd B = cmul(W[0], cd{zz.x, zz.y});
-          const double phi = c1 * p;
-          const double a = fma(h1, p2, 1.0);
-          W[1] = cd{fma(B.re, a, -B.im * phi), fma(B.im, a, B.re * phi)};
-        }
-#pragma unroll
-        for (int c = 0; c < CT; ++c) {
-          const double2 be = q[c];
-#pragma unroll
-          for (int r = 0; r < R; ++r) cfma_conj(acc[r][c], W[r], cd{be.x, be.y});
-        }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          m0[r] = cadd(m0[r], W[r]);
-          m1[r].re = fma(p, W[r].re, m1[r].re);
-          m1[r].im = fma(p, W[r].im, m1[r].im);
-          m2[r].re = fma(p2, W[r].re, m2[r].re);
-          m2[r].im = fma(p2, W[r].im, m2[r].im);
+          W[r] = Srow[r];
+          T0[r] = cadd(T0[r], Srow[r]);
+          T1[r] = cd{fma(fa, Srow[r].re, T1[r].re), fma(fa, Srow[r].im, T1[r].im)};
+          T2[r] = cd{fma(fa2, Srow[r].re, T2[r].re), fma(fa2, Srow[r].im, T2[r].im)};
+        }
+#pragma unroll 2
+        for (int v = 0; v < B; ++v) {
+          const double2* q = rec + v * RS;
+#pragma unroll
+          for (int c = 0; c < CT; ++c) {
+            const double2 be = q[c];
+#pragma unroll
+            for (int r = 0; r < R; ++r) cfma_conj(acc[r][c], W[r], cd{be.x, be.y});
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) W[r] = cmul(W[r], Vst[r]);
+        }
+        // start of the next lattice row
+        if (((arow + 1) & 7) == 0) {
+          const double pa = fma((double)(arow + 1), pg1, po);
+#pragma unroll
+          for (int r = 0; r < R; ++r) Srow[r] = expi_tab(tab, dte[r], pa);
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) Srow[r] = cmul(Srow[r], Ust[r]);
+        }
+      }
+      // R_q,t = sum_j p_j^q W_jt with p_j = po + a pg1 + b pg2 and
+      // W_jt = E U^a V^b, from T_k and SV_k = sum_b b^k V^b:
+      //   R0 = X, R1 = po X + pg1 Y + pg2 Z,
+      //   R2 = po (po X + 2 pg1 Y + 2 pg2 Z) + pg1^2 Q + pg2^2 S + 2 pg1 pg2 N,
+      // X = T0 SV0, Y = T1 SV0, Z = T0 SV1, Q = T2 SV0, S = T0 SV2, N = T1 SV1.
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        cd sv0 = cd{0.0, 0.0}, sv1 = sv0, sv2 = sv0, vb = cd{1.0, 0.0};
+        for (int b = 0; b < B; ++b) {
+          const double fb = (double)b, fb2 = fb * fb;
+          sv0 = cadd(sv0, vb);
+          sv1 = cd{fma(fb, vb.re, sv1.re), fma(fb, vb.im, sv1.im)};
+          sv2 = cd{fma(fb2, vb.re, sv2.re), fma(fb2, vb.im, sv2.im)};
+          vb = cmul(vb, Vst[r]);
+        }
+        const cd X = cmul(T0[r], sv0), Y = cmul(T1[r], sv0), Z = cmul(T0[r], sv1);
+        const cd Q = cmul(T2[r], sv0), S2 = cmul(T0[r], sv2), N = cmul(T1[r], sv1);
+        m0[r] = X;
+        m1[r] = cd{fma(pg2, Z.re, fma(pg1, Y.re, po * X.re)), fma(pg2, Z.im, fma(pg1, Y.im, po * X.im))};
+        const double g1 = 2.0 * pg1, g2 = 2.0 * pg2, g12 = 2.0 * pg1 * pg2;
+        const double pg1s = pg1 * pg1, pg2s = pg2 * pg2;
+        const double lre = fma(g2, Z.re, fma(g1, Y.re, po * X.re));
+        const double lim = fma(g2, Z.im, fma(g1, Y.im, po * X.im));
+        m2[r] = cd{fma(g12, N.re, fma(pg2s, S2.re, fma(pg1s, Q.re, po * lre))),
+                   fma(g12, N.im, fma(pg2s, S2.im, fma(pg1s, Q.im, po * lim)))};
+      }
+    } else {
+      const double dtl = kPhaseTab * T.m.e[lane];
+      double c1 = 0.0, h1 = 0.0, dtz = 0.0;
+      if constexpr (R > 1) {
+        c1 = kTwoPi * ((T.m.e[lane + 16] - T.m.e[lane]) - T.m.e[16]);
+        h1 = -0.5 * c1 * c1;
+        dtz = kPhaseTab * T.m.e[16];
+      }
+      fetch(0);
+      for (int j0 = 0; j0 < m; j0 += kViewBatch) {
+        produce(j0, kViewBatch, dtz, true);
+        const int nv = min(kViewBatch, m - j0);
+#pragma unroll 2
+        for (int v = 0; v < nv; ++v) {
+          const double2* q = rec + v * RS;
+          const double2 pp = q[CT + 1];
+          const double p = pp.x, p2 = pp.y;
+          cd W[R];
+          W[0] = expi_tab(tab, dtl, p);
+          if constexpr (R > 1) {
+            const double2 zz = q[CT];
+            const cd Bz = cmul(W[0], cd{zz.x, zz.y});
+            const double phi = c1 * p;
+            const double a = fma(h1, p2, 1.0);
+            W[1] = cd{fma(Bz.re, a, -Bz.im * phi), fma(Bz.im, a, Bz.re * phi)};
+          }
+#pragma unroll
+          for (int c = 0; c < CT; ++c) {
+            const double2 be = q[c];
+#pragma unroll
+            for (int r = 0; r < R; ++r) cfma_conj(acc[r][c], W[r], cd{be.x, be.y});
+          }
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            m0[r] = cadd(m0[r], W[r]);
+            m1[r].re = fma(p, W[r].re, m1[r].re);
+            m1[r].im = fma(p, W[r].im, m1[r].im);
+            m2[r].re = fma(p2, W[r].re, m2[r].re);
+            m2[r].im = fma(p2, W[r].im, m2[r].im);
+          }
         }
       }
     }
