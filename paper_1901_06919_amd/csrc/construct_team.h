@@ -902,7 +902,7 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
         s.re = allreduce16(s.re);
         s.im = allreduce16(s.im);
         const cd xi = cscale(csub(acc[0][c], s), invd[0]);
-        acc[0][c] = lane == i ? xi : acc[0][c];
+        acc[0][c] = csel(lane == i, xi, acc[0][c]);
       }
       sched_fence();
     });

@@ -37,6 +37,9 @@ __device__ __forceinline__ cd cmulc(cd a, cd b) {
   return cd{fma(a.re, b.re, a.im * b.im), fma(a.re, b.im, -a.im * b.re)};
 }
 __device__ __forceinline__ cd cscale(cd a, double s) { return cd{a.re * s, a.im * s}; }
+// c ? a : b per component: a select of the whole struct on a lane-varying
+// condition can be lowered through scratch memory instead of two v_cndmask
+__device__ __forceinline__ cd csel(bool c, cd a, cd b) { return cd{c ? a.re : b.re, c ? a.im : b.im}; }
 // acc += conj(a) * b
 __device__ __forceinline__ void cfma_conj(cd& acc, cd a, cd b) {
   acc.re = fma(a.re, b.re, acc.re);
