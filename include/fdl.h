@@ -132,7 +132,12 @@ int fdl_irfft2(fdl_c64* spec_dev, float* img_dev, int batch, int H, int W, void*
  * the DC bin solvable (remark after Eq. 2ndOrderView), added outside lambda.
  *
  *   view_spec_dev  [m][C][H][W/2+1] complex64  (b_j = spectrum of view j)
- *   u_dev          [m] fdl_f2                  view positions
+ *   u_dev          [m] fdl_f2                  view positions (any values).  With
+ *                  Toeplitz sums (below) and positions on an exact lattice in
+ *                  raster order, u_j = u_0 + a g1 + b g2 for j = a B + b with
+ *                  B <= 16 (checked on the device in FP64), the phases are
+ *                  stepped from view to view and the moment sums taken in
+ *                  closed form; the result is the same up to rounding.
  *   d_host         [n] float32, HOST memory     layer disparities (any values);
  *                  read during the call and passed to the kernels by value.
  *                  When they form an arithmetic progression up to float rounding
