@@ -248,6 +248,9 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
         hj += v.re * v.re + v.im * v.im;
       }
     }
+    // column t + C of P is read whole above before the thread that owns it
+    // (t + C, possibly in another wave) scales its last row below
+    __syncthreads();
     // backward: row n-1 scaled, then steps k = n-1 .. 1
     for (int col = t; col < ncol; col += NT) stc(el(n - 1, col), 0, cscale(ldc(el(n - 1, col), 0), inv[n - 1]));
     __syncthreads();

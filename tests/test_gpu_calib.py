@@ -43,7 +43,12 @@ def _small(seed, m, n, C, H, W):
 
 @pytest.mark.parametrize("mode", [O.LOSS_FIT, O.LOSS_LOO])
 @pytest.mark.parametrize("m,n,C,H,W,reg", [(5, 3, 1, 8, 8, O.REG_LAYER2), (9, 7, 2, 12, 16, O.REG_LAYER2),
-                                           (16, 16, 1, 8, 12, O.REG_L2), (4, 6, 3, 6, 8, O.REG_LAYER2)])
+                                           (16, 16, 1, 8, 12, O.REG_L2), (4, 6, 3, 6, 8, O.REG_LAYER2),
+                                           # more than 64 right-hand-side columns (C + m): the triangular
+                                           # sweeps span several waves, and with 3 channels one wave takes
+                                           # more than 64 columns (m = 255)
+                                           (70, 6, 2, 6, 8, O.REG_LAYER2), (81, 8, 1, 4, 6, O.REG_VIEW2),
+                                           (255, 4, 3, 2, 4, O.REG_L2)])
 def test_calib_small_all_bins(mode, m, n, C, H, W, reg):
     print(f"calib mode={mode} m={m} n={n} C={C} H={H} W={W} reg={reg}", flush=True)
     u, d, spec, F = _small(100 + m + n, m, n, C, H, W)
