@@ -1,6 +1,7 @@
 """GPU parity at the benchmark's full size, in the launch configuration the
 benchmark times: 9x9 views, 512x512 RGB, 30 layers linspace(-3,3,30) on the
-jittered grid (Toeplitz construction kernel, 3 channels), and 81 disk renders.
+jittered grid (Toeplitz construction kernel, 3 channels; also on the exact
+grid, the lattice path of that kernel), and 81 disk renders.
 The oracle checks sampled outputs: construction on a seeded subset of bins
 plus the DC, Nyquist and edge bins; rendering on a subset of the 81 views,
 every bin of each."""
@@ -44,6 +45,34 @@ def test_construct_9x9_512_rgb_full_size_sampled_bins():
     edge = [0, 1, Wh - 1, (H // 2) * Wh, (H // 2) * Wh + Wh - 1, (H - 1) * Wh, F - 1]
     idx = np.unique(np.concatenate([synth.frequency_subset(F, 2048, rng), edge]))
     ref = O.construct(spec.astype(np.complex128), lfb.u.astype(np.float64), lfb.d.astype(np.float64), H, W,
+                      lfb.lam, lfb.eps, lfb.reg, freq_index=idx)
+    got = x.cpu().numpy().reshape(30, 3, F)[:, :, idx]
+    err = O.rel_l2(got, ref)
+    errs = [O.rel_l2(got[:, :, i], ref[:, :, i]) for i in range(len(idx))]
+    worst = float("inf") if any(e != e for e in errs) else max(errs)   # NaN counts as a failure
+    print(f"  {len(idx)} bins: rel_l2 {err:.3e}, worst bin {worst:.3e}, status {st.item()}")
+    assert err < TOL and worst < TOL
+    assert st.item() == 0
+
+
+def test_construct_9x9_512_rgb_exact_grid_full_size_sampled_bins():
+    """The same workload on the exact 9x9 integer grid (no jitter): the views
+    form a lattice in raster order, so the construction steps the phases
+    from view to view and takes the moments in closed form."""
+    lfb = synth.lf_9x9_512_rgb()
+    u = synth.grid_positions(4)
+    H, W = 512, 512
+    Wh = W // 2 + 1
+    F = H * Wh
+    rng = np.random.default_rng(951)
+    spec = _spectra(rng, (81, 3, H, Wh))
+    print("construct 81 views (exact grid) 512x512 RGB 30 layers, all bins on the GPU", flush=True)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    x = fdl().construct(dev(spec), dev(u), torch.from_numpy(lfb.d), H, W, lfb.lam, lfb.eps, lfb.reg, status=st)
+    torch.cuda.synchronize()
+    edge = [0, 1, Wh - 1, (H // 2) * Wh, (H // 2) * Wh + Wh - 1, (H - 1) * Wh, F - 1]
+    idx = np.unique(np.concatenate([synth.frequency_subset(F, 2048, rng), edge]))
+    ref = O.construct(spec.astype(np.complex128), u.astype(np.float64), lfb.d.astype(np.float64), H, W,
                       lfb.lam, lfb.eps, lfb.reg, freq_index=idx)
     got = x.cpu().numpy().reshape(30, 3, F)[:, :, idx]
     err = O.rel_l2(got, ref)
