@@ -100,7 +100,10 @@ __device__ __forceinline__ double reg_entry(int reg, int i, int k, int n, double
 // RELAXED: the relaxed model of Sec. VIII-B, phases <P_jk, w> from a free
 // shift matrix and the gradient with respect to every shift (Eq. gradP with
 // both components) instead of the chain rule to u and d.
-template <bool RELAXED>
+// NR > 0 (n <= NR, leave-one-out loss): each right-hand-side column of the
+// triangular sweeps is held in the registers of one thread (below); NR = 0:
+// the sweeps run in LDS.
+template <bool RELAXED, int NR>
 __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
   constexpr int NT = 256;
   extern __shared__ double sm[];
@@ -216,52 +219,108 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
 
     // Triangular sweeps over a set of right-hand-side columns: the C
     // right-hand sides of x and, for the leave-one-out loss, the m columns of
-    // P = conj(A)^T (so that P becomes L^-1 A^H, then G = L^-H P).  Each step
-    // updates with the final row k and scales the row that became final, so
-    // one barrier per step.
+    // P = conj(A)^T (so that P becomes L^-1 A^H, then G = L^-H P).
     double* Pm = sm + o.P;
     const int ncol = C + (P.mode == 1 ? m : 0);
     auto el = [&](int i, int col) -> double* { return col < C ? x + 2 * (i * C + col) : Pm + 2 * (i * m + col - C); };
-    if (P.mode == 1) {
-      for (int e = t; e < n * m; e += NT) {
-        const int k = e / m, j = e - k * m;
-        stc(Pm, e, cd{A[2 * (j * n + k)], -A[2 * (j * n + k) + 1]});
-      }
-      __syncthreads();
-    }
-    // forward: row 0 scaled, then steps k = 0 .. n-2
-    for (int col = t; col < ncol; col += NT) stc(el(0, col), 0, cscale(ldc(el(0, col), 0), inv[0]));
-    __syncthreads();
-    for (int k = 0; k + 1 < n; ++k) {
-      for (int e = t; e < (n - k - 1) * ncol; e += NT) {
-        const int i = k + 1 + e / ncol, col = e % ncol;
-        cd v = csub(ldc(el(i, col), 0), cmul(ldc(L, i * n + k), ldc(el(k, col), 0)));
-        if (i == k + 1) v = cscale(v, inv[i]);
-        stc(el(i, col), 0, v);
-      }
-      __syncthreads();
-    }
     double hj = 0.0;
-    if (P.mode == 1 && t < m) {
-      for (int k = 0; k < n; ++k) {
-        const cd v = ldc(Pm, k * m + t);
-        hj += v.re * v.re + v.im * v.im;
-      }
-    }
-    // column t + C of P is read whole above before the thread that owns it
-    // (t + C, possibly in another wave) scales its last row below
-    __syncthreads();
-    // backward: row n-1 scaled, then steps k = n-1 .. 1
-    for (int col = t; col < ncol; col += NT) stc(el(n - 1, col), 0, cscale(ldc(el(n - 1, col), 0), inv[n - 1]));
-    __syncthreads();
-    for (int k = n - 1; k > 0; --k) {
-      for (int e = t; e < k * ncol; e += NT) {
-        const int i = e / ncol, col = e % ncol;
-        cd v = csub(ldc(el(i, col), 0), cmulc(ldc(L, k * n + i), ldc(el(k, col), 0)));
-        if (i == k - 1) v = cscale(v, inv[i]);
-        stc(el(i, col), 0, v);
+    if (NR > 0 && ncol >= 32) {
+      // One thread per column, the column in registers: forward and backward
+      // substitution with the entries of L broadcast from LDS, in the order of
+      // the LDS sweeps below.  The leverage h_j = ||P_:j||^2 of a P column is
+      // parked in gam[j] (not yet in use) for thread j.
+      double* gam = sm + o.gam;
+      for (int col = t; col < ncol; col += NT) {
+        const int j = col - C;
+        constexpr int NRR = NR > 0 ? NR : 1;
+        cd v[NRR];
+#pragma unroll
+        for (int i = 0; i < NRR; ++i) {
+          v[i] = cd{0.0, 0.0};
+          if (i < n) v[i] = col < C ? ldc(x, i * C + col) : cd{A[2 * (j * n + i)], -A[2 * (j * n + i) + 1]};
+        }
+        v[0] = cscale(v[0], inv[0]);
+#pragma unroll
+        for (int k = 0; k + 1 < NRR; ++k) {
+#pragma unroll
+          for (int i = k + 1; i < NRR; ++i) {
+            if (i < n) {
+              cd w = csub(v[i], cmul(ldc(L, i * n + k), v[k]));
+              if (i == k + 1) w = cscale(w, inv[i]);
+              v[i] = w;
+            }
+          }
+        }
+        if (j >= 0) {
+          double h = 0.0;
+#pragma unroll
+          for (int i = 0; i < NRR; ++i)
+            if (i < n) h += v[i].re * v[i].re + v[i].im * v[i].im;
+          gam[j] = h;
+        }
+#pragma unroll
+        for (int i = 0; i < NRR; ++i)
+          if (i == n - 1) v[i] = cscale(v[i], inv[i]);
+#pragma unroll
+        for (int k = NRR - 1; k > 0; --k) {
+          if (k < n) {
+#pragma unroll
+            for (int i = 0; i < k; ++i) {
+              cd w = csub(v[i], cmulc(ldc(L, k * n + i), v[k]));
+              if (i == k - 1) w = cscale(w, inv[i]);
+              v[i] = w;
+            }
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NRR; ++i)
+          if (i < n) stc(el(i, col), 0, v[i]);
       }
       __syncthreads();
+      if (P.mode == 1 && t < m) hj = gam[t];
+    } else {
+      // LDS sweeps: each step updates with the final row k and scales the row
+      // that became final, one barrier per step.
+      if (P.mode == 1) {
+        for (int e = t; e < n * m; e += NT) {
+          const int k = e / m, j = e - k * m;
+          stc(Pm, e, cd{A[2 * (j * n + k)], -A[2 * (j * n + k) + 1]});
+        }
+        __syncthreads();
+      }
+      // forward: row 0 scaled, then steps k = 0 .. n-2
+      for (int col = t; col < ncol; col += NT) stc(el(0, col), 0, cscale(ldc(el(0, col), 0), inv[0]));
+      __syncthreads();
+      for (int k = 0; k + 1 < n; ++k) {
+        for (int e = t; e < (n - k - 1) * ncol; e += NT) {
+          const int i = k + 1 + e / ncol, col = e % ncol;
+          cd v = csub(ldc(el(i, col), 0), cmul(ldc(L, i * n + k), ldc(el(k, col), 0)));
+          if (i == k + 1) v = cscale(v, inv[i]);
+          stc(el(i, col), 0, v);
+        }
+        __syncthreads();
+      }
+      if (P.mode == 1 && t < m) {
+        for (int k = 0; k < n; ++k) {
+          const cd v = ldc(Pm, k * m + t);
+          hj += v.re * v.re + v.im * v.im;
+        }
+      }
+      // column t + C of P is read whole above before the thread that owns it
+      // (t + C, possibly in another wave) scales its last row below
+      __syncthreads();
+      // backward: row n-1 scaled, then steps k = n-1 .. 1
+      for (int col = t; col < ncol; col += NT) stc(el(n - 1, col), 0, cscale(ldc(el(n - 1, col), 0), inv[n - 1]));
+      __syncthreads();
+      for (int k = n - 1; k > 0; --k) {
+        for (int e = t; e < k * ncol; e += NT) {
+          const int i = e / ncol, col = e % ncol;
+          cd v = csub(ldc(el(i, col), 0), cmulc(ldc(L, k * n + i), ldc(el(k, col), 0)));
+          if (i == k - 1) v = cscale(v, inv[i]);
+          stc(el(i, col), 0, v);
+        }
+        __syncthreads();
+      }
     }
     // residual: FIT r = A x - b ; LOO r = b - A x
     const double rs = P.mode == 1 ? -1.0 : 1.0;
@@ -435,7 +494,7 @@ int calib_blocks(int Q, size_t lds_per_block) {
   return Q < (int)nb ? Q : (int)nb;
 }
 
-template <bool RELAXED>
+template <bool RELAXED, int NR>
 static hipError_t launch_calib_t(const CalibParams& P, hipStream_t s) {
   const size_t lds = calib_lds_bytes(P.m, P.n, P.C, P.mode, RELAXED);
   const int nb = calib_blocks(P.Q, lds);
@@ -443,11 +502,11 @@ static hipError_t launch_calib_t(const CalibParams& P, hipStream_t s) {
   // device; it is set on every such launch (a host-side call, no stream
   // work), so no process-wide state decides it for another device or thread.
   if (lds > 65536) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_calib<RELAXED>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_calib<RELAXED, NR>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(k_calib<RELAXED>, dim3(nb), dim3(256), lds, s, P);
+  hipLaunchKernelGGL((k_calib<RELAXED, NR>), dim3(nb), dim3(256), lds, s, P);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_calib_reduce, dim3(P.stride), dim3(256), 0, s, P, nb);
@@ -455,7 +514,12 @@ static hipError_t launch_calib_t(const CalibParams& P, hipStream_t s) {
 }
 
 hipError_t launch_calib(const CalibParams& P, hipStream_t s) {
-  return P.shifts ? launch_calib_t<true>(P, s) : launch_calib_t<false>(P, s);
+  // register sweeps for the leave-one-out loss (C + m >= 32 columns) with at
+  // most 16 layers; the paper loss (C columns) keeps the LDS sweeps in a
+  // kernel without the register path, whose spills would slow it down
+  if (P.mode == 1 && P.n <= 16 && P.C + P.m >= 32)
+    return P.shifts ? launch_calib_t<true, 16>(P, s) : launch_calib_t<false, 16>(P, s);
+  return P.shifts ? launch_calib_t<true, 0>(P, s) : launch_calib_t<false, 0>(P, s);
 }
 
 // Partial-sum buffer of the allocation-free calibration entry point: a
