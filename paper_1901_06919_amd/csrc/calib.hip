@@ -383,13 +383,22 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
         for (int j = 0; j < m; ++j) cfma(s, ldc(Pm, k * m + j), ldc(w, j * C + c));
         stc(y, i, s);
       }
-      // Wm[p][k] = sum_i A_ip gam_i G_ki
-      for (int e = t; e < n * n; e += NT) {
-        const int p = e / n, k = e - p * n;
-        cd s = cd{0.0, 0.0};
+      // Wm[p][k] = sum_i A_ip gam_i G_ki, two entries (p, k) and (p, k + h2)
+      // per thread sharing the factor A_ip gam_i
+      const int h2 = (n + 1) >> 1;
+      for (int e = t; e < n * h2; e += NT) {
+        const int p = e / h2, k = e - p * h2;
+        const bool two = k + h2 < n;
+        const int k1 = two ? k + h2 : k;
+        cd s0 = cd{0.0, 0.0}, s1 = cd{0.0, 0.0};
         #pragma unroll 4
-        for (int i = 0; i < m; ++i) cfma(s, cscale(ldc(A, i * n + p), gam[i]), ldc(Pm, k * m + i));
-        stc(Wm, e, s);
+        for (int i = 0; i < m; ++i) {
+          const cd ag = cscale(ldc(A, i * n + p), gam[i]);
+          cfma(s0, ag, ldc(Pm, k * m + i));
+          cfma(s1, ag, ldc(Pm, k1 * m + i));
+        }
+        stc(Wm, p * n + k, s0);
+        if (two) stc(Wm, p * n + k1, s1);
       }
       __syncthreads();
       // v = w - A y
@@ -400,19 +409,32 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
         stc(v, i, s);
       }
       __syncthreads();
-      for (int i = t; i < m * n; i += NT) {
-        const int j = i / n, k = i - j * n;
-        cd psi = cscale(ldc(Pm, k * m + j), gam[j]);
+      // two entries (j, k) and (j, k + h2) per thread sharing G_pj, v_j and r_j
+      for (int e = t; e < m * h2; e += NT) {
+        const int j = e / h2, k = e - j * h2;
+        const bool two = k + h2 < n;
+        const int k1 = two ? k + h2 : k;
+        cd psi0 = cscale(ldc(Pm, k * m + j), gam[j]);
+        cd psi1 = cscale(ldc(Pm, k1 * m + j), gam[j]);
         for (int c = 0; c < C; ++c) {
-          const cd vv = ldc(v, j * C + c), xx = ldc(x, k * C + c);
-          const cd rr = ldc(r, j * C + c), yy = ldc(y, k * C + c);
-          psi = csub(psi, cmulc(vv, xx));
-          psi = csub(psi, cmulc(rr, yy));
+          const cd vv = ldc(v, j * C + c), rr = ldc(r, j * C + c);
+          psi0 = csub(psi0, cmulc(vv, ldc(x, k * C + c)));
+          psi0 = csub(psi0, cmulc(rr, ldc(y, k * C + c)));
+          psi1 = csub(psi1, cmulc(vv, ldc(x, k1 * C + c)));
+          psi1 = csub(psi1, cmulc(rr, ldc(y, k1 * C + c)));
         }
         #pragma unroll 4
-        for (int p = 0; p < n; ++p) psi = csub(psi, cmul(ldc(Pm, p * m + j), ldc(Wm, p * n + k)));
-        const cd pa = cmul(psi, ldc(A, i));
-        T[i] = -4.0 * kPi * pa.im;
+        for (int p = 0; p < n; ++p) {
+          const cd g = ldc(Pm, p * m + j);
+          psi0 = csub(psi0, cmul(g, ldc(Wm, p * n + k)));
+          psi1 = csub(psi1, cmul(g, ldc(Wm, p * n + k1)));
+        }
+        const cd pa0 = cmul(psi0, ldc(A, j * n + k));
+        T[j * n + k] = -4.0 * kPi * pa0.im;
+        if (two) {
+          const cd pa1 = cmul(psi1, ldc(A, j * n + k1));
+          T[j * n + k1] = -4.0 * kPi * pa1.im;
+        }
       }
     }
     __syncthreads();
