@@ -141,7 +141,7 @@ def cpu_baseline(views_img, u, d, lam, eps, reg, render_views, calib):
     and the leave-one-out calibration gradient on 256 of the 4096 sampled
     bins of the calibration workload.  Work is split over worker threads
     (numpy's FFT, LAPACK and ufuncs release the GIL; BLAS pinned to one
-    thread each); every stage runs once to warm up, then 3 times, and the
+    thread each); every stage runs once to warm up, then 5 times, and the
     median is reported, scaled to the benchmark's units."""
     import concurrent.futures
 
@@ -157,7 +157,7 @@ def cpu_baseline(views_img, u, d, lam, eps, reg, render_views, calib):
     def med(fn):
         fn()
         ts = []
-        for _ in range(3):
+        for _ in range(5):
             t0 = time.perf_counter()
             fn()
             ts.append(time.perf_counter() - t0)
@@ -205,7 +205,7 @@ def cpu_baseline(views_img, u, d, lam, eps, reg, render_views, calib):
     except OSError:
         pass
     return {"value": F / t_con, "unit": "bins/s", "cores": workers, "kind": "oracle",
-            "sample": (f"FP64 oracle on the benchmark's inputs, {workers} threads, median of 3 after a warm-up: "
+            "sample": (f"FP64 oracle on the benchmark's inputs, {workers} threads, median of 5 after a warm-up: "
                        f"rfft2 of {m * C} images {H}x{W} ({t_fft:.2f} s), construction of all {F} bins "
                        f"({t_con:.2f} s), disk render of {rv.shape[0]} of the views ({t_ren:.2f} s), LOO gradient on "
                        f"256 of {cidx.shape[0]} bins of the 7x7/256^2 calibration workload (scaled)"),
