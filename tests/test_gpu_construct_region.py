@@ -45,6 +45,35 @@ def test_construct_region_matches_oracle(grid, n, C, H, W, region, uniform):
     assert st.item() == 0
 
 
+# one case per kernel instantiation: row slots (n <= 16 or not) x channel class
+# (1, 2-3, 4) x disparity class (uniform on an exact grid, general on a
+# jittered one)
+REGION_CLASSES = [(n, C, uniform) for n in (12, 21) for C in (1, 3, 4) for uniform in (True, False)]
+
+
+@pytest.mark.parametrize("n,C,uniform", REGION_CLASSES)
+def test_construct_region_every_instantiation(n, C, uniform):
+    print(f"construct_region class n={n} C={C} uniform={uniform}", flush=True)
+    rng = np.random.default_rng(1200 + 7 * n + C)
+    u = synth.centered_grid_positions(3).astype(np.float32)
+    if not uniform:
+        u = u + rng.uniform(-0.3, 0.3, u.shape).astype(np.float32)
+    m = u.shape[0]
+    H, W = 10, 12
+    d = (np.linspace(-2, 2, n) if uniform else np.sort(rng.uniform(-2, 2, n))).astype(np.float32)
+    spec = O.rfft2(rng.standard_normal((m, C, H, W))).astype(np.complex64)
+    lam, eps, region = 0.05, 1e-3, 3.0
+    ref = O.construct(spec.astype(np.complex128), u.astype(np.float64), d.astype(np.float64), H, W, lam, eps,
+                      O.REG_VIEW2_REGION, region=region)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    got = fdl().construct_region(dev(spec), dev(u), torch.from_numpy(d), H, W, lam, eps, region, status=st)
+    torch.cuda.synchronize()
+    err = O.rel_l2(got.cpu().numpy(), ref)
+    print(f"  rel_l2 {err:.3e} status {st.item()}")
+    assert err < TOL
+    assert st.item() == 0
+
+
 def test_construct_region_large_side_is_the_view_regulariser():
     H, W = 32, 32
     rng = np.random.default_rng(910)
