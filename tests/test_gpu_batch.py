@@ -66,6 +66,59 @@ def test_batched_matches_plain_calls(mode):
         assert O.rel_l2(it["out"].cpu().numpy(), r.cpu().numpy()) < 1e-6
 
 
+def _mixed_items(seed):
+    """A batch that spans every batched kernel class: 1, 2, 3 and 4 channels,
+    uniform and general disparities, exact and jittered view grids (lattice
+    and table paths), 5 to 32 layers."""
+    rng = np.random.default_rng(seed)
+    items = []
+    for i, (g, side, n, C, uniform, jitter) in enumerate([
+            (3, 64, 5, 1, True, False), (4, 96, 12, 2, True, True), (5, 64, 20, 3, False, True),
+            (3, 128, 32, 4, True, False), (5, 96, 27, 1, False, False), (4, 64, 16, 4, False, True),
+            (3, 96, 30, 3, True, True), (2, 64, 8, 2, False, False), (4, 128, 24, 1, True, True),
+            (3, 64, 29, 4, True, True)]):
+        u = synth.centered_grid_positions(g)
+        if jitter:
+            u = (u + rng.uniform(-0.05, 0.05, u.shape)).astype(np.float32)
+        m = u.shape[0]
+        H = W = side
+        spec = (rng.standard_normal((m, C, H, W // 2 + 1)) + 1j * rng.standard_normal((m, C, H, W // 2 + 1)))
+        spec = spec.astype(np.complex64)
+        d = (np.linspace(-2.0, 2.0, n) if uniform else np.sort(rng.uniform(-2.0, 2.0, n))).astype(np.float32)
+        items.append(dict(spec_np=spec, u_np=u, d_np=d, H=H, W=W, lam=1e-2, eps=1e-3, reg=0,
+                          view_spec=torch.from_numpy(spec).cuda(), u=torch.from_numpy(u).cuda(),
+                          d=torch.from_numpy(d).cuda(),
+                          out=torch.empty((n, C, H, W // 2 + 1), dtype=torch.complex64, device="cuda")))
+    return items
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_batched_mixed_classes_match_plain_calls(mode):
+    items = _mixed_items(40 + mode)
+    print(f"mixed batch mode {mode}: {len(items)} light fields", flush=True)
+    ref = _plain(items)
+    plan = fdl().BatchPlan(items, mode=mode)
+    plan.execute()
+    torch.cuda.synchronize()
+    worst = 0.0
+    for it, r in zip(items, ref):
+        e = O.rel_l2(it["out"].cpu().numpy(), r.cpu().numpy())
+        worst = max(worst, e) if e == e else float("inf")   # NaN counts as a failure
+    print(f"  launches {plan.launches}, worst rel_l2 vs plain {worst:.2e}")
+    assert worst < 1e-6
+    # one light field of each kind against the oracle on a few bins
+    rng = np.random.default_rng(7)
+    for it in items[:4]:
+        F = it["H"] * (it["W"] // 2 + 1)
+        idx = np.unique(np.concatenate([[0, F - 1], rng.choice(F, 24, replace=False)]))
+        refo = O.construct(it["spec_np"].astype(np.complex128), it["u_np"].astype(np.float64),
+                           it["d_np"].astype(np.float64), it["H"], it["W"], it["lam"], it["eps"], it["reg"],
+                           freq_index=idx)
+        n, C = it["out"].shape[:2]
+        got = it["out"].cpu().numpy().reshape(n, C, F)[:, :, idx]
+        assert O.rel_l2(got, refo) < 1e-4
+
+
 def test_batched_matches_oracle_on_sampled_bins():
     items = _items(6, sizes=(128, 384, 512), seed=11)
     plan = fdl().BatchPlan(items, mode=1)
