@@ -63,7 +63,9 @@ def test_hybrid_pinholes_disks_squares_three_channels():
     assert _check(views, d, len(views), 3, 40, 36, 1e-2, 1e-3, O.REG_LAYER2, 2) < TOL
 
 
-@pytest.mark.parametrize("n,C", [(5, 2), (32, 4)])
+# (5, 2) and (32, 4) as before, plus the other instantiations of the kernel:
+# row slots (n <= 16 or not) x channel class (1, 2-3, 4)
+@pytest.mark.parametrize("n,C", [(5, 2), (32, 4), (9, 1), (14, 4), (20, 1), (26, 3)])
 def test_views_small_and_largest(n, C):
     print(f"construct_views m=9 n={n} C={C} 12x16", flush=True)
     rng = np.random.default_rng(n)

@@ -43,7 +43,9 @@ def _spectra(rng, m, C, H, W):
 
 @pytest.mark.parametrize("m,n,C,H,W,reg", [(9, 5, 1, 24, 40, O.REG_LAYER2), (13, 20, 3, 16, 24, O.REG_L2),
                                            (6, 32, 4, 8, 12, O.REG_LAYER2), (1, 1, 1, 2, 2, O.REG_L2),
-                                           (25, 16, 2, 20, 18, O.REG_LAYER2)])
+                                           (25, 16, 2, 20, 18, O.REG_LAYER2),
+                                           # the remaining instantiations: R = 1 with 4 channels, R = 2 with 1
+                                           (10, 12, 4, 10, 12, O.REG_LAYER2), (12, 24, 1, 12, 14, O.REG_L2)])
 def test_construct_relaxed_matches_oracle(m, n, C, H, W, reg):
     print(f"construct_relaxed m={m} n={n} C={C} H={H} W={W} reg={reg}", flush=True)
     rng = np.random.default_rng(700 + m + n)
