@@ -80,6 +80,20 @@ def test_host_side_validation_without_gpu():
     assert L.fdl_server_create(ctypes.c_size_t(1 << 30), 4, 65, 0, ctypes.byref(h)) == -1
     assert L.fdl_server_submit(None, None, None) == -1
     assert L.fdl_server_destroy(None) == -1
+    # empty inputs are rejected, never launched: no views, layers, images, bins
+    # or samples, an empty bin range, an empty batch
+    assert L.fdl_construct(fake, fake, d, 0, 4, 1, 8, 8, 0.01, 0.001, 0, fake, None, None) == -2
+    assert L.fdl_construct(fake, fake, d, 4, 0, 1, 8, 8, 0.01, 0.001, 0, fake, None, None) == -2
+    assert L.fdl_construct_bins(fake, fake, d, 4, 4, 1, 8, 8, 0.01, 0.001, 0, 0, 0, fake, None, None) == -1
+    assert L.fdl_construct_bins(fake, fake, d, 4, 4, 1, 8, 8, 0.01, 0.001, 0, 30, 11, fake, None, None) == -1
+    assert L.fdl_construct_bins(fake, fake, d, 4, 4, 1, 8, 8, 0.01, 0.001, 0, -1, 4, fake, None, None) == -1
+    assert L.fdl_rfft2(fake, fake, 0, 8, 8, None) == -2
+    assert L.fdl_irfft2(fake, fake, 0, 8, 8, None) == -2
+    assert L.fdl_render(fake, fake, 4, 1, 8, 8, fake, 0, fake, None) == -2
+    assert L.fdl_calib_grad(fake, fake, fake, 4, 4, 1, 8, 8, 0.01, 0.001, 1, 1, fake, 0,
+                            fake, fake, fake, None, fake, 1 << 20, None) == -1
+    plan = ctypes.c_void_p()
+    assert L.fdl_batch_plan_create(fake, 0, 0, ctypes.byref(plan)) == -1
     # finite-region view regulariser: the region side must be finite and positive
     assert L.fdl_construct_region(fake, fake, d, 4, 4, 1, 8, 8, 0.01, 0.001, 0.0, fake, None, None) == -1
     assert L.fdl_construct_region(fake, fake, d, 4, 40, 1, 8, 8, 0.01, 0.001, 2.0, fake, None, None) == -2
