@@ -352,6 +352,11 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
   double pmax = 0.0;
 
   // ---- 1-2: stream the views ----
+  // The view loop runs at a raised wave priority, the factorisation at the
+  // default: with two waves per SIMD, the wave in the view loop (LDS reads,
+  // independent accumulators) then takes the issue slots that the other
+  // wave's dependent DPP chains leave (measured 2-3.5 % on the 30-row kernel).
+  __builtin_amdgcn_s_setprio(1);
   // Channels c >= C (CT > C) read channel C - 1; their sums are never stored.
   const size_t F = (size_t)P.F;
   const int m = P.m;
@@ -790,6 +795,7 @@ __device__ __forceinline__ void team_solve(const ConstructParams& P, TeamLds<R>&
 #pragma unroll
     for (int c = 0; c < CT; ++c) T.rhs.c[lane][r * CT + c] = make_double2(acc[r][c].re, acc[r][c].im);
 
+  __builtin_amdgcn_s_setprio(0);
   // ---- 4: Cholesky ----
   bool bad = false;
   double invd[R];
