@@ -278,6 +278,39 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
       }
       __syncthreads();
       if (P.mode == 1 && t < m) hj = gam[t];
+    } else if (NR == 0 && P.mode == 0 && n <= 16) {
+      // Paper loss: the C <= 4 columns of x, one 16-lane team of wave 0 each,
+      // row i in lane i.  Each step broadcasts the final value of row k from
+      // lane k (DPP) into the updates of the other rows, with L read from
+      // LDS; no block barrier until the columns are stored.
+      if (t < 64) {
+        const int col = t >> 4, l = t & 15;
+        const bool live = col < C && l < n;
+        cd v = live ? ldc(x, l * C + col) : cd{0.0, 0.0};
+        const double il = l < n ? inv[l] : 0.0;
+        // forward: x_k = v_k / L_kk is final at step k; rows i > k subtract L_ik x_k
+        static_for<0, 16>([&](auto KK) {
+          constexpr int k = decltype(KK)::value;
+          if (k + 1 < n) {
+            const cd y = cscale(v, il);
+            const cd lk = l > k && l < n ? ldc(L, l * n + k) : cd{0.0, 0.0};
+            dpp_cfms<k>(v, lk, y);
+          }
+        });
+        v = cscale(v, il);
+        // backward: x_k = w_k / L_kk is final at step k; rows i < k subtract conj(L_ki) x_k
+        static_for<0, 16>([&](auto KK) {
+          constexpr int k = 15 - decltype(KK)::value;
+          if (k >= 1 && k < n) {
+            const cd y = cscale(v, il);
+            const cd lk = l < k ? ldc(L, k * n + l) : cd{0.0, 0.0};
+            dpp_cfms_conja<k>(v, lk, y);
+          }
+        });
+        v = cscale(v, il);
+        if (live) stc(x, l * C + col, v);
+      }
+      __syncthreads();
     } else {
       // LDS sweeps: each step updates with the final row k and scales the row
       // that became final, one barrier per step.
