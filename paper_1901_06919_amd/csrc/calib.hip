@@ -100,9 +100,10 @@ __device__ __forceinline__ double reg_entry(int reg, int i, int k, int n, double
 // RELAXED: the relaxed model of Sec. VIII-B, phases <P_jk, w> from a free
 // shift matrix and the gradient with respect to every shift (Eq. gradP with
 // both components) instead of the chain rule to u and d.
-// NR > 0 (n <= NR, leave-one-out loss): each right-hand-side column of the
-// triangular sweeps is held in the registers of one thread (below); NR = 0:
-// the sweeps run in LDS.
+// NR > 0 (n <= NR <= 16, leave-one-out loss): the right-hand-side columns of
+// the triangular sweeps are swept by the 16-lane teams of the block, one row
+// per lane (below); NR = 0: the sweeps run in LDS, or for the paper loss with
+// n <= 16 in the teams of wave 0.
 template <bool RELAXED, int NR>
 __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
   constexpr int NT = 256;
@@ -211,8 +212,16 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
         cfms_aconjb(v, cscale(ldc(L, i * n + j), ip), ldc(L, k * n + j));
         stc(L, i * n + k, v);
       }
+      // (leave-one-out kernel) the scaled column j-1 is also mirrored,
+      // conjugated, into row j-1 of the upper triangle (unused otherwise),
+      // where the team sweeps read it with consecutive lanes on consecutive
+      // entries
       if (j > 0)
-        for (int i = j + t; i < n; i += NT) stc(L, i * n + j - 1, cscale(ldc(L, i * n + j - 1), inv[j - 1]));
+        for (int i = j + t; i < n; i += NT) {
+          const cd v = cscale(ldc(L, i * n + j - 1), inv[j - 1]);
+          stc(L, i * n + j - 1, v);
+          if constexpr (NR > 0) stc(L, (j - 1) * n + i, cd{v.re, -v.im});
+        }
       if (t == 0) inv[j] = 1.0 / sqrt(piv);
       __syncthreads();
     }
@@ -225,56 +234,60 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
     auto el = [&](int i, int col) -> double* { return col < C ? x + 2 * (i * C + col) : Pm + 2 * (i * m + col - C); };
     double hj = 0.0;
     if (NR > 0 && ncol >= 32) {
-      // One thread per column, the column in registers: forward and backward
-      // substitution with the entries of L broadcast from LDS, in the order of
-      // the LDS sweeps below.  The leverage h_j = ||P_:j||^2 of a P column is
-      // parked in gam[j] (not yet in use) for thread j.
+      // Leave-one-out loss, n <= 16: every 16-lane team of the block sweeps
+      // four columns at a time, row i in lane i (columns team + 16 r of each
+      // group of 64).  Each step broadcasts the final value of row k from lane
+      // k (DPP) into the other rows' updates; L comes from LDS, the forward
+      // sweep reading its conjugated mirror in the upper triangle.  The
+      // leverage h_j = ||P_:j||^2 of a P column is parked in gam[j] (not yet
+      // in use) for thread j.
       double* gam = sm + o.gam;
-      for (int col = t; col < ncol; col += NT) {
-        const int j = col - C;
-        constexpr int NRR = NR > 0 ? NR : 1;
-        cd v[NRR];
+      const int team = t >> 4, l = t & 15;
+      const double il = l < n ? inv[l] : 0.0;
+      for (int c0 = 0; c0 < ncol; c0 += 64) {
+        cd v[4];
 #pragma unroll
-        for (int i = 0; i < NRR; ++i) {
-          v[i] = cd{0.0, 0.0};
-          if (i < n) v[i] = col < C ? ldc(x, i * C + col) : cd{A[2 * (j * n + i)], -A[2 * (j * n + i) + 1]};
+        for (int r = 0; r < 4; ++r) {
+          const int col = c0 + team + 16 * r, j = col - C;
+          v[r] = cd{0.0, 0.0};
+          if (col < ncol && l < n) v[r] = col < C ? ldc(x, l * C + col) : cd{A[2 * (j * n + l)], -A[2 * (j * n + l) + 1]};
         }
-        v[0] = cscale(v[0], inv[0]);
+        // forward: y_k = v_k / L_kk is final at step k; rows i > k subtract L_ik y_k
+        static_for<0, 16>([&](auto KK) {
+          constexpr int k = decltype(KK)::value;
+          if (k + 1 < n) {
+            const cd lk = l > k && l < n ? ldc(L, k * n + l) : cd{0.0, 0.0};   // conj(L_lk)
+            cd y[4];
 #pragma unroll
-        for (int k = 0; k + 1 < NRR; ++k) {
-#pragma unroll
-          for (int i = k + 1; i < NRR; ++i) {
-            if (i < n) {
-              cd w = csub(v[i], cmul(ldc(L, i * n + k), v[k]));
-              if (i == k + 1) w = cscale(w, inv[i]);
-              v[i] = w;
-            }
+            for (int r = 0; r < 4; ++r) y[r] = cscale(v[r], il);
+            dpp_cfms_conja2<k, k>(v[0], lk, y[0], v[1], lk, y[1]);
+            dpp_cfms_conja2<k, k>(v[2], lk, y[2], v[3], lk, y[3]);
           }
+        });
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          v[r] = cscale(v[r], il);
+          const int col = c0 + team + 16 * r;
+          const double h = allreduce16(v[r].re * v[r].re + v[r].im * v[r].im);
+          if (l == 0 && col >= C && col < ncol) gam[col - C] = h;
         }
-        if (j >= 0) {
-          double h = 0.0;
+        // backward: x_k = w_k / L_kk is final at step k; rows i < k subtract conj(L_ki) x_k
+        static_for<0, 16>([&](auto KK) {
+          constexpr int k = 15 - decltype(KK)::value;
+          if (k >= 1 && k < n) {
+            const cd lk = l < k ? ldc(L, k * n + l) : cd{0.0, 0.0};
+            cd y[4];
 #pragma unroll
-          for (int i = 0; i < NRR; ++i)
-            if (i < n) h += v[i].re * v[i].re + v[i].im * v[i].im;
-          gam[j] = h;
-        }
-#pragma unroll
-        for (int i = 0; i < NRR; ++i)
-          if (i == n - 1) v[i] = cscale(v[i], inv[i]);
-#pragma unroll
-        for (int k = NRR - 1; k > 0; --k) {
-          if (k < n) {
-#pragma unroll
-            for (int i = 0; i < k; ++i) {
-              cd w = csub(v[i], cmulc(ldc(L, k * n + i), v[k]));
-              if (i == k - 1) w = cscale(w, inv[i]);
-              v[i] = w;
-            }
+            for (int r = 0; r < 4; ++r) y[r] = cscale(v[r], il);
+            dpp_cfms_conja2<k, k>(v[0], lk, y[0], v[1], lk, y[1]);
+            dpp_cfms_conja2<k, k>(v[2], lk, y[2], v[3], lk, y[3]);
           }
-        }
+        });
 #pragma unroll
-        for (int i = 0; i < NRR; ++i)
-          if (i < n) stc(el(i, col), 0, v[i]);
+        for (int r = 0; r < 4; ++r) {
+          const int col = c0 + team + 16 * r;
+          if (col < ncol && l < n) stc(el(l, col), 0, cscale(v[r], il));
+        }
       }
       __syncthreads();
       if (P.mode == 1 && t < m) hj = gam[t];
