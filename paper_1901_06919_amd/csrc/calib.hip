@@ -204,13 +204,21 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
       double piv = L[2 * (j * n + j)];
       if (!(piv > 0.0)) piv = 1e-300;
       const double ip = 1.0 / piv;
-      const int rem = n - j - 1;
-      for (int e = t; e < rem * rem; e += NT) {
-        const int i = j + 1 + e / rem, k = j + 1 + e % rem;
-        if (k > i) continue;
+      auto update = [&](int i, int k) {
         cd v = ldc(L, i * n + k);
         cfms_aconjb(v, cscale(ldc(L, i * n + j), ip), ldc(L, k * n + j));
         stc(L, i * n + k, v);
+      };
+      if (n <= 16) {
+        // the trailing block fits a fixed 16 x 16 grid of threads
+        const int i = j + 1 + (t >> 4), k = j + 1 + (t & 15);
+        if (i < n && k <= i) update(i, k);
+      } else {
+        const int rem = n - j - 1;
+        for (int e = t; e < rem * rem; e += NT) {
+          const int i = j + 1 + e / rem, k = j + 1 + e % rem;
+          if (k <= i) update(i, k);
+        }
       }
       // (leave-one-out kernel) the scaled column j-1 is also mirrored,
       // conjugated, into row j-1 of the upper triangle (unused otherwise),
