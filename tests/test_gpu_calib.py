@@ -48,7 +48,10 @@ def _small(seed, m, n, C, H, W):
                                            # sweeps span several waves, and with 3 channels one wave takes
                                            # more than 64 columns (m = 255)
                                            (70, 6, 2, 6, 8, O.REG_LAYER2), (81, 8, 1, 4, 6, O.REG_VIEW2),
-                                           (255, 4, 3, 2, 4, O.REG_L2)])
+                                           (255, 4, 3, 2, 4, O.REG_L2),
+                                           # an odd layer count below 16: the 16-lane teams run with
+                                           # three idle lanes (both losses take the team paths)
+                                           (40, 13, 2, 6, 8, O.REG_VIEW2)])
 def test_calib_small_all_bins(mode, m, n, C, H, W, reg):
     print(f"calib mode={mode} m={m} n={n} C={C} H={H} W={W} reg={reg}", flush=True)
     u, d, spec, F = _small(100 + m + n, m, n, C, H, W)
