@@ -198,12 +198,18 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
     // the trailing matrix with the unscaled column j (L_ik -= L_ij conj(L_kj) /
     // piv_j) and scales column j-1, which no thread reads any more.  Only
     // inv[j] = 1 / L_jj is kept: the diagonal itself is read by every thread
-    // as the pivot and is never overwritten (nothing later reads it).
+    // as the pivot and is never overwritten (nothing later reads it).  Every
+    // thread forms 1 / L_jj from the hardware reciprocal square root and two
+    // Newton steps, and 1 / piv_j as its square (a few instructions, where a
+    // correctly rounded division and square root take dozens).
     double* inv = sm + o.inv;
     for (int j = 0; j < n; ++j) {
       double piv = L[2 * (j * n + j)];
-      if (!(piv > 0.0)) piv = 1e-300;
-      const double ip = 1.0 / piv;
+      if (!(piv > 0.0 && isfinite(piv))) piv = 1e-300;
+      double rq = __builtin_amdgcn_rsq(piv);
+      rq = rq * fma(-0.5 * piv * rq, rq, 1.5);
+      rq = rq * fma(-0.5 * piv * rq, rq, 1.5);
+      const double ip = rq * rq;
       auto update = [&](int i, int k) {
         cd v = ldc(L, i * n + k);
         cfms_aconjb(v, cscale(ldc(L, i * n + j), ip), ldc(L, k * n + j));
@@ -230,7 +236,7 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
           stc(L, i * n + j - 1, v);
           if constexpr (NR > 0) stc(L, (j - 1) * n + i, cd{v.re, -v.im});
         }
-      if (t == 0) inv[j] = 1.0 / sqrt(piv);
+      if (t == 0) inv[j] = rq;
       __syncthreads();
     }
 
