@@ -104,12 +104,28 @@ __device__ __forceinline__ double reg_entry(int reg, int i, int k, int n, double
 // the triangular sweeps are swept by the 16-lane teams of the block, one row
 // per lane (below); NR = 0: the sweeps run in LDS, or for the paper loss with
 // n <= 16 in the teams of wave 0.
+// i / d for 0 <= i < 2^24 and d >= 1 without an integer division: the
+// float quotient (relative error below 2^-23) is within one of the exact
+// one, and one step on the integer remainder corrects it.
+struct FastDiv {
+  int d;
+  float inv;
+  __device__ explicit FastDiv(int d_) : d(d_), inv(1.0f / (float)d_) {}
+  __device__ int operator()(int i) const {
+    int q = (int)((float)i * inv);
+    const int r = i - q * d;
+    q += r >= d ? 1 : (r < 0 ? -1 : 0);
+    return q;
+  }
+};
+
 template <bool RELAXED, int NR>
 __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
   constexpr int NT = 256;
   extern __shared__ double sm[];
   const int m = P.m, n = P.n, C = P.C;
   const CalibLayout o = calib_layout(m, n, C, P.mode, RELAXED);
+  const FastDiv div_n(n), div_C(C), div_nn(n * n);
   double* A = sm + o.A;
   double* L = sm + o.L;
   double* b = sm + o.b;
@@ -166,7 +182,7 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
     fetch(q + gridDim.x);
     __syncthreads();
     for (int i = t; i < m * n; i += NT) {
-      const int j = i / n, k = i - j * n;
+      const int j = div_n(i), k = i - j * n;
       if constexpr (RELAXED) {
         const float2 sh = P.shifts[i];
         stc(A, i, expi2pi(fma((double)sh.x, wx, (double)sh.y * wy)));
@@ -177,7 +193,7 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
     __syncthreads();
     // normal matrix (lower triangle, full storage) and right-hand sides
     for (int i = t; i < n * n; i += NT) {
-      const int k1 = i / n, k2 = i - k1 * n;
+      const int k1 = div_n(i), k2 = i - k1 * n;
       if (k2 > k1) continue;
       cd s = cd{0.0, 0.0};
       #pragma unroll 4
@@ -187,7 +203,7 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
       stc(L, i, s);
     }
     for (int i = t; i < n * C; i += NT) {
-      const int k = i / C, c = i - k * C;
+      const int k = div_C(i), c = i - k * C;
       cd s = cd{0.0, 0.0};
       #pragma unroll 4
       for (int j = 0; j < m; ++j) cfma_conj(s, ldc(A, j * n + k), ldc(b, j * C + c));
@@ -385,7 +401,7 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
     // residual: FIT r = A x - b ; LOO r = b - A x
     const double rs = P.mode == 1 ? -1.0 : 1.0;
     for (int i = t; i < m * C; i += NT) {
-      const int j = i / C, c = i - j * C;
+      const int j = div_C(i), c = i - j * C;
       cd s = cd{0.0, 0.0};
       #pragma unroll 4
       for (int k = 0; k < n; ++k) cfma(s, ldc(A, j * n + k), ldc(x, k * C + c));
@@ -398,7 +414,7 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
       // loss: ||r||^2 + x^H (lambda G + eps I) x, split over lanes
       for (int i = t; i < m * C; i += NT) { const cd v = ldc(r, i); loss += v.re * v.re + v.im * v.im; }
       for (int i = t; i < n * n * C; i += NT) {
-        const int c = i / (n * n), e = i - c * n * n, k1 = e / n, k2 = e - k1 * n;
+        const int c = div_nn(i), e = i - c * n * n, k1 = div_n(e), k2 = e - k1 * n;
         const double g =
             reg_entry(P.reg, k1, k2, n, P.lambda, w4, RELAXED ? 0.0 : (double)P.d[k1]) + (k1 == k2 ? P.eps : 0.0);
         if (g != 0.0) {
@@ -407,7 +423,7 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
         }
       }
       for (int i = t; i < m * n; i += NT) {
-        const int j = i / n, k = i - j * n;
+        const int j = div_n(i), k = i - j * n;
         const cd a = ldc(A, i);
         double s = 0.0;
         for (int c = 0; c < C; ++c) {
@@ -437,7 +453,7 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
       __syncthreads();
       // y = G w
       for (int i = t; i < n * C; i += NT) {
-        const int k = i / C, c = i - k * C;
+        const int k = div_C(i), c = i - k * C;
         cd s = cd{0.0, 0.0};
         #pragma unroll 4
         for (int j = 0; j < m; ++j) cfma(s, ldc(Pm, k * m + j), ldc(w, j * C + c));
@@ -446,8 +462,9 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
       // Wm[p][k] = sum_i A_ip gam_i G_ki, two entries (p, k) and (p, k + h2)
       // per thread sharing the factor A_ip gam_i
       const int h2 = (n + 1) >> 1;
+      const FastDiv div_h2(h2);
       for (int e = t; e < n * h2; e += NT) {
-        const int p = e / h2, k = e - p * h2;
+        const int p = div_h2(e), k = e - p * h2;
         const bool two = k + h2 < n;
         const int k1 = two ? k + h2 : k;
         cd s0 = cd{0.0, 0.0}, s1 = cd{0.0, 0.0};
@@ -463,7 +480,7 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
       __syncthreads();
       // v = w - A y
       for (int i = t; i < m * C; i += NT) {
-        const int j = i / C, c = i - j * C;
+        const int j = div_C(i), c = i - j * C;
         cd s = ldc(w, i);
         for (int k = 0; k < n; ++k) s = csub(s, cmul(ldc(A, j * n + k), ldc(y, k * C + c)));
         stc(v, i, s);
@@ -471,7 +488,7 @@ __global__ __launch_bounds__(256, 4) void k_calib(CalibParams P) {
       __syncthreads();
       // two entries (j, k) and (j, k + h2) per thread sharing G_pj, v_j and r_j
       for (int e = t; e < m * h2; e += NT) {
-        const int j = e / h2, k = e - j * h2;
+        const int j = div_h2(e), k = e - j * h2;
         const bool two = k + h2 < n;
         const int k1 = two ? k + h2 : k;
         cd psi0 = cscale(ldc(Pm, k * m + j), gam[j]);
