@@ -613,9 +613,10 @@ static hipError_t launch_calib_t(const CalibParams& P, hipStream_t s) {
 }
 
 hipError_t launch_calib(const CalibParams& P, hipStream_t s) {
-  // register sweeps for the leave-one-out loss (C + m >= 32 columns) with at
-  // most 16 layers; the paper loss (C columns) keeps the LDS sweeps in a
-  // kernel without the register path, whose spills would slow it down
+  // team sweeps over all waves for the leave-one-out loss (C + m >= 32
+  // columns) with at most 16 layers; every other case, the paper loss among
+  // them (its C columns swept by the teams of wave 0), runs the kernel
+  // without that path, which spills less
   if (P.mode == 1 && P.n <= 16 && P.C + P.m >= 32)
     return P.shifts ? launch_calib_t<true, 16>(P, s) : launch_calib_t<false, 16>(P, s);
   return P.shifts ? launch_calib_t<true, 0>(P, s) : launch_calib_t<false, 0>(P, s);
