@@ -103,22 +103,30 @@ __device__ __forceinline__ float jinc_tab(const float4* __restrict__ tab, float 
   return fmaf(fmaf(fmaf(c.w, t, c.z), t, c.y), t, c.x);
 }
 
+// x0 mod N in [0, N) for an integer-valued float x0: the quotient from a
+// multiply by 1/N, then one correction step.  Every step is exact in float
+// for |x0| < 2^24, so this equals the floored division; the clamp keeps any
+// other input inside the table.
+__device__ __forceinline__ int wrap_index(float x0, float fN, float invN) {
+  float r = x0 - fN * floorf(x0 * invN);
+  r = r < 0.0f ? r + fN : (r >= fN ? r - fN : r);
+  return min(max((int)r, 0), (int)fN - 1);
+}
+
 // psi_hat of a drawn aperture from its table of spectrum samples (N x N,
 // rows k_y): bilinear interpolation at the continuous sample index (tx, ty),
-// periodic in both directions; indices are reduced in float and clamped, so
-// every read stays inside the table.
-__device__ __forceinline__ float2 aperture_tab(const float2* __restrict__ tab, int N, float tx, float ty) {
-  const float fN = (float)N;
+// periodic in both directions.  The four samples are buffer loads with
+// 32-bit byte offsets (N <= 2048: the table holds at most 2^25 bytes).
+__device__ __forceinline__ float2 aperture_tab(__amdgpu_buffer_rsrc_t tab, int N, float fN, float invN, float tx,
+                                               float ty) {
   const float x0 = floorf(tx), y0 = floorf(ty);
   const float fx = tx - x0, fy = ty - y0;
-  int ix = (int)(x0 - fN * floorf(x0 / fN));
-  int iy = (int)(y0 - fN * floorf(y0 / fN));
-  ix = min(max(ix, 0), N - 1);
-  iy = min(max(iy, 0), N - 1);
+  const int ix = wrap_index(x0, fN, invN), iy = wrap_index(y0, fN, invN);
   const int ix1 = ix + 1 == N ? 0 : ix + 1;
   const int iy1 = iy + 1 == N ? 0 : iy + 1;
-  const float2 a = tab[(size_t)iy * N + ix], b = tab[(size_t)iy * N + ix1];
-  const float2 c = tab[(size_t)iy1 * N + ix], e = tab[(size_t)iy1 * N + ix1];
+  const unsigned r0 = (unsigned)(iy * N) * 8u, r1 = (unsigned)(iy1 * N) * 8u;
+  const float2 a = buf_load_f2(tab, r0 + (unsigned)ix * 8u, 0), b = buf_load_f2(tab, r0 + (unsigned)ix1 * 8u, 0);
+  const float2 c = buf_load_f2(tab, r1 + (unsigned)ix * 8u, 0), e = buf_load_f2(tab, r1 + (unsigned)ix1 * 8u, 0);
   const float w00 = (1.f - fx) * (1.f - fy), w01 = fx * (1.f - fy), w10 = (1.f - fx) * fy, w11 = fx * fy;
   return make_float2(w00 * a.x + w01 * b.x + w10 * c.x + w11 * e.x, w00 * a.y + w01 * b.y + w10 * c.y + w11 * e.y);
 }
@@ -149,6 +157,9 @@ __global__ __launch_bounds__(256) void k_render(RenderParams P, int nchunks) {
   const float wn = sqrtf(wx * wx + wy * wy);
   const int C = P.C;
   const size_t F = (size_t)P.F;
+  // drawn-aperture table (TAB kernels only)
+  const __amdgpu_buffer_rsrc_t tabr = buf_rsrc(TAB ? (const void*)P.ap_tab : (const void*)P.layer_spec);
+  const float apN = (float)P.ap_N, apInv = TAB ? 1.0f / apN : 0.0f;
 
   // per view: <u0, w>, focus, and the aperture scale of |s - d_k|:
   // disk z = 2 pi rho |w| |s - d|, square arguments 2 rho w_x (s - d), 2 rho w_y (s - d)
@@ -210,7 +221,7 @@ __global__ __launch_bounds__(256) void k_render(RenderParams P, int nchunks) {
         float g = 1.0f;
         float pr, pi;
         if (TAB && kind[v] == 3) {
-          const float2 q = aperture_tab(P.ap_tab, P.ap_N, g1[v] * a, g2[v] * a);
+          const float2 q = aperture_tab(tabr, P.ap_N, apN, apInv, g1[v] * a, g2[v] * a);
           pr = co * q.x - s * q.y;
           pi = s * q.x + co * q.y;
         } else {
